@@ -1,0 +1,149 @@
+"""Invariants of the seeded inputs (impurity coefficients and operator
+strings).  Checked with the oracle's full-space operators.  CPU only."""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.fock import annihilators, occupations
+from oracle.hamiltonian import hamiltonian_sparse
+from workloads import make_configs, make_impurity
+from workloads.configs import SPECS
+from workloads.impurity import clebsch_gordan, coupled_basis_matrix, shell_coupled, wigner_3j, _slater_F
+
+
+def test_wigner_3j_known_values():
+    assert wigner_3j(1, 1, 0, 0, 0, 0) == pytest.approx(-1 / math.sqrt(3), abs=1e-15)
+    assert wigner_3j(1, 1, 2, 1, -1, 0) == pytest.approx(math.sqrt(1 / 30), abs=1e-15)
+    assert wigner_3j(3, 2, 3, 0, 0, 0) == pytest.approx(2 / math.sqrt(105), abs=1e-15)  # (-1)^g sqrt(...) g!/..., g = 4
+    assert clebsch_gordan(0.5, 0.5, 0.5, -0.5, 1, 0) == pytest.approx(1 / math.sqrt(2), abs=1e-15)
+    assert clebsch_gordan(1, 1, 0.5, -0.5, 0.5, 0.5) == pytest.approx(math.sqrt(2 / 3), abs=1e-15)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_coupled_basis_is_orthogonal(l):
+    T, twomj = coupled_basis_matrix(l)
+    assert np.allclose(T @ T.T, np.eye(2 * (2 * l + 1)), atol=1e-14)
+    assert list(twomj[: 2 * l]) == list(range(-(2 * l - 1), 2 * l, 2))
+
+
+@pytest.mark.parametrize("name", ["kanamori2", "dshell", "pshell", "fshell", "fshell_cf", "dd_fshell"])
+def test_hermiticity(name):
+    imp = make_impurity(name)
+    assert np.allclose(imp.h1, imp.h1.conj().T, atol=1e-14)
+    # (c+_i c+_j c_k c_l)^+ = c+_l c+_k c_j c_i
+    assert np.allclose(imp.U, np.conj(imp.U.transpose(3, 2, 1, 0)), atol=1e-13)
+
+
+def _level_multiplicities(E, tol=1e-8):
+    E = np.sort(E)
+    out, cur = [], 1
+    for a, b in zip(E[:-1], E[1:]):
+        if b - a < tol:
+            cur += 1
+        else:
+            out.append(cur)
+            cur = 1
+    out.append(cur)
+    return out
+
+
+def _restrict(H, nf, N):
+    idx = np.nonzero(occupations(nf).sum(axis=1) == N)[0]
+    return H[idx][:, idx].toarray()
+
+
+def test_f2_LS_terms():
+    """xi = 0: the two-electron f levels are the LS terms 1S 3P 1D 3F 1G 3H 1I
+    with multiplicities 1 9 5 21 9 33 13."""
+    h1, U, _ = shell_coupled(3, _slater_F(5.0, 0.512), 0.0)
+    H = hamiltonian_sparse(h1, U)
+    E = np.linalg.eigvalsh(_restrict(H, 14, 2))
+    assert sorted(_level_multiplicities(E)) == sorted([1, 9, 5, 21, 9, 33, 13])
+
+
+def test_f1_spin_orbit_levels():
+    imp = make_impurity("fshell_real")
+    H = hamiltonian_sparse(imp.h1, imp.U)
+    E = np.sort(np.linalg.eigvalsh(_restrict(H, 14, 1)))
+    xi, mu = imp.params["xi"], imp.params["mu"]
+    assert np.allclose(E, sorted([-2 * xi - mu] * 6 + [1.5 * xi - mu] * 8), atol=1e-12)
+
+
+def test_kanamori_two_orbital_two_electron_spectrum():
+    imp = make_impurity("kanamori2")
+    H = hamiltonian_sparse(imp.h1, imp.U)
+    E = np.sort(np.linalg.eigvalsh(_restrict(H, 4, 2))) + 2 * 4.75
+    U, J = 4.0, 0.5
+    assert np.allclose(E, sorted([U - 3 * J] * 3 + [U - J] * 2 + [U + J]), atol=1e-12)
+
+
+def _jz_and_j2(l):
+    nf = 2 * (2 * l + 1)
+    c = annihilators(nf)
+    _, twomj = coupled_basis_matrix(l)
+    Jz = sum(0.5 * twomj[f] * (c[f].T @ c[f]) for f in range(nf))
+    Jp = sp.csr_matrix(Jz.shape)
+    off = 0
+    for j2 in (2 * l - 1, 2 * l + 1):
+        j = j2 / 2
+        for k in range(j2):  # m = -j + k -> m + 1
+            m = -j + k
+            Jp = Jp + math.sqrt(j * (j + 1) - m * (m + 1)) * (c[off + k + 1].T @ c[off + k])
+        off += j2 + 1
+    Jm = Jp.T
+    J2 = Jz @ Jz + 0.5 * (Jp @ Jm + Jm @ Jp)
+    return Jz, J2
+
+
+def _comm_norm(A, B):
+    C = A @ B - B @ A
+    return abs(C).max() if C.nnz else 0.0
+
+
+def test_fshell_symmetries():
+    real = make_impurity("fshell_real")
+    gauged = make_impurity("fshell")
+    cf = make_impurity("fshell_cf")
+    Jz, J2 = _jz_and_j2(3)
+    N = sp.diags(occupations(14).sum(axis=1).astype(float))
+    Hr = hamiltonian_sparse(real.h1, real.U)
+    Hg = hamiltonian_sparse(gauged.h1, gauged.U)
+    Hc = hamiltonian_sparse(cf.h1, cf.U)
+    assert _comm_norm(Hr, N) < 1e-12 and _comm_norm(Hr, Jz) < 1e-12
+    assert _comm_norm(Hr, J2) < 1e-10
+    assert _comm_norm(Hg, N) < 1e-12 and _comm_norm(Hg, Jz) < 1e-12
+    assert _comm_norm(Hc, N) < 1e-12
+    assert _comm_norm(Hc, Jz) > 1e-3   # the crystal field breaks Jz
+    assert gauged.is_complex and cf.is_complex and not real.is_complex
+
+
+def test_dshell_symmetries():
+    imp = make_impurity("dshell")
+    H = hamiltonian_sparse(imp.h1, imp.U)
+    occ = occupations(10)
+    N = sp.diags(occ.sum(axis=1).astype(float))
+    Sz = sp.diags((occ @ np.array([-1] * 5 + [1] * 5)).astype(float))
+    assert _comm_norm(H, N) < 1e-12 and _comm_norm(H, Sz) < 1e-12
+    assert 3 <= imp.params["U"] <= 6 and 0.5 <= imp.params["J"] <= 1
+
+
+@pytest.mark.parametrize("cid", [0, 1, 2, 3])
+def test_config_strings(cid):
+    spec = SPECS[cid]
+    cfgs = make_configs(cid, 50)
+    again = make_configs(cid, 5)
+    nf = {0: 4, 1: 10, 2: 14, 3: 14}[cid]
+    beta = {0: 10.0, 1: 50.0, 2: 40.0, 3: 40.0}[cid]
+    for a, b in zip(cfgs[:5], again):
+        assert np.array_equal(a.op, b.op) and np.array_equal(a.tau, b.tau)
+    for c in cfgs:
+        assert c.n % 2 == 0 and spec.order_lo <= c.n <= spec.order_hi
+        assert np.all(np.diff(c.tau) >= 0) and (c.n == 0 or (c.tau[0] > 0 and c.tau[-1] < beta))
+        for f in range(nf):
+            ops_f = c.op[c.op // 2 == f]
+            assert np.sum(ops_f % 2 == 1) == np.sum(ops_f % 2 == 0)
+            if spec.rule == "alternating":
+                assert np.all(np.diff(ops_f % 2) != 0)

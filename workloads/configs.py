@@ -1,0 +1,107 @@
+"""Seeded operator strings: the configurations C of the hybridisation
+expansion (Sec. 2.2), already time ordered.
+
+A string is (tau, op): times 0 <= tau_0 <= ... < beta and operator codes
+op = 2*flavor + dagger (dagger = 1 for a creator).  op[0] at tau[0] acts
+first (rightmost in the product).  Every flavor carries as many creators as
+annihilators, as in the configurations the Markov chain visits.
+
+Two type rules:
+  * "random":      per flavor, the k creators and k annihilators are placed
+                   on that flavor's 2k time slots in random order;
+  * "alternating": per flavor, creators and annihilators alternate in time
+                   with a random first type.  Markov states reached by the
+                   Pauli-aware pair moves of App. D have this form (a flavor
+                   cannot be created twice in a row).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .impurity import IMPURITY_SHAPE
+
+
+@dataclasses.dataclass
+class OperatorString:
+    tau: np.ndarray  # float64 [n]
+    op: np.ndarray   # int32 [n]
+
+    @property
+    def n(self) -> int:
+        return int(self.op.shape[0])
+
+
+def random_string(rng: np.random.Generator, n_flavors: int, beta: float, n_ops: int,
+                  rule: str = "alternating") -> OperatorString:
+    if n_ops % 2:
+        raise ValueError("n_ops must be even")
+    pairs = rng.multinomial(n_ops // 2, [1.0 / n_flavors] * n_flavors)
+    taus, ops = [], []
+    for f, k in enumerate(pairs):
+        if k == 0:
+            continue
+        t = np.sort(rng.uniform(0.0, beta, 2 * k))
+        if rule == "alternating":
+            first = int(rng.integers(2))
+            dag = (np.arange(2 * k) + first) % 2
+        elif rule == "random":
+            dag = rng.permutation(np.array([0] * k + [1] * k))
+        else:
+            raise ValueError(rule)
+        taus.append(t)
+        ops.append(2 * f + dag)
+    if not taus:
+        return OperatorString(np.zeros(0), np.zeros(0, dtype=np.int32))
+    tau = np.concatenate(taus)
+    op = np.concatenate(ops).astype(np.int32)
+    order = np.argsort(tau, kind="stable")
+    return OperatorString(tau[order].astype(np.float64), op[order])
+
+
+@dataclasses.dataclass(frozen=True)
+class WorkloadSpec:
+    config_id: int
+    impurity: str
+    n_configs: int
+    order_lo: int
+    order_hi: int
+    rule: str
+
+
+SPECS = {
+    0: WorkloadSpec(0, "kanamori2", 1000, 0, 20, "random"),
+    1: WorkloadSpec(1, "dshell", 10_000, 20, 80, "alternating"),
+    2: WorkloadSpec(2, "fshell", 10_000, 40, 160, "alternating"),
+    3: WorkloadSpec(3, "fshell_cf", 2000, 60, 200, "alternating"),
+}
+
+
+def config_string(config_id: int, i: int, spec: WorkloadSpec | None = None,
+                  n_flavors: int | None = None, beta: float | None = None) -> OperatorString:
+    """Configuration i of a workload, seeded by PCG64(10^6 * config_id + i)."""
+    spec = spec or SPECS[config_id]
+    if n_flavors is None or beta is None:
+        n_flavors, beta = IMPURITY_SHAPE[spec.impurity]
+    rng = np.random.Generator(np.random.PCG64(1_000_000 * config_id + i))
+    n = 2 * int(rng.integers(spec.order_lo // 2, spec.order_hi // 2 + 1))
+    return random_string(rng, n_flavors, beta, n, spec.rule)
+
+
+def make_configs(config_id: int, count: int | None = None, start: int = 0,
+                 spec: WorkloadSpec | None = None) -> list[OperatorString]:
+    spec = spec or SPECS[config_id]
+    count = spec.n_configs - start if count is None else count
+    n_flavors, beta = IMPURITY_SHAPE[spec.impurity]
+    return [config_string(config_id, start + i, spec, n_flavors, beta) for i in range(count)]
+
+
+def pack(strings: list[OperatorString]):
+    """Concatenate strings into CSR form: (offsets int64[n+1], tau f64, op i32)."""
+    offs = np.zeros(len(strings) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([s.n for s in strings])
+    tau = np.concatenate([s.tau for s in strings]) if strings else np.zeros(0)
+    op = np.concatenate([s.op for s in strings]).astype(np.int32) if strings else np.zeros(0, np.int32)
+    return offs, np.ascontiguousarray(tau, dtype=np.float64), np.ascontiguousarray(op, dtype=np.int32)
