@@ -4,14 +4,18 @@
     P(x) = exp(-x H_loc).
 
 Two independent routes:
-  * DenseTrace: diagonalise H_loc once (LAPACK eigh), carry every operator to
-    the eigenbasis (V^H C V), where P(x) is diagonal;
+  * DenseTrace: diagonalise H_loc once (LAPACK eigh on each connected
+    component of its nonzero pattern, assembled into one full-space unitary
+    V), carry every operator to the eigenbasis (V^H C V, a full 2^n x 2^n
+    matrix), where P(x) is diagonal;
   * expm_trace: stay in the occupation-number basis and form every P(x) with
     scipy's matrix exponential (no eigendecomposition), for tiny spaces.
 
-Magnitudes: after every operator the running product X is divided by a power
-of two (2^e, e from frexp of max|X|); the exponents are summed.  The result is
-returned as (mantissa, log_scale) with w_loc = mantissa * exp(log_scale).
+Magnitudes: every column of the running product X carries its own log scale.
+Propagators take out the factor of the column's lowest occupied energy, and
+after every operator the column is divided by a power of two (exact).  The
+result is returned as (mantissa, log_scale) with w_loc = mantissa *
+exp(log_scale).
 """
 
 from __future__ import annotations
@@ -20,11 +24,38 @@ import math
 
 import numpy as np
 import scipy.linalg
+from scipy.sparse.csgraph import connected_components
 
 from .fock import operator
-from .hamiltonian import hamiltonian_dense
+from .hamiltonian import hamiltonian_dense, hamiltonian_sparse
 
 LN2 = math.log(2.0)
+
+
+def _eigh_keeping_zeros(H):
+    """Eigen-decomposition H = V diag(E) V^H of the full-space matrix.
+
+    The eigenvectors are computed separately on every connected component of
+    the graph of H's nonzero entries (the smallest subspaces H leaves
+    invariant), so V has exact zeros wherever H's powers do.  A single dense
+    eigh of the whole matrix may mix degenerate levels that belong to
+    different invariant subspaces; the trace is unchanged in exact arithmetic,
+    but rounding then couples contributions that differ by many orders of
+    magnitude at low temperature and the small ones are lost."""
+    D = H.shape[0]
+    pattern = (abs(H) > 0).astype(np.int8)
+    n_comp, comp = connected_components(pattern, directed=False)
+    E = np.zeros(D)
+    V = np.zeros((D, D), dtype=H.dtype)
+    pos = 0
+    for k in range(n_comp):
+        idx = np.nonzero(comp == k)[0]
+        e, v = scipy.linalg.eigh(H[idx][:, idx].toarray())
+        E[pos:pos + idx.size] = e
+        V[idx, pos:pos + idx.size] = v
+        pos += idx.size
+    order = np.argsort(E, kind="stable")
+    return E[order], V[:, order]
 
 
 def _check_string(tau, op, beta, n_flavors):
@@ -39,12 +70,52 @@ def _check_string(tau, op, beta, n_flavors):
     return tau, op
 
 
-def _rescale(X):
-    m = float(np.max(np.abs(X))) if X.size else 0.0
-    if m == 0.0:
-        return X, 0, True
-    e = math.frexp(m)[1]
-    return X * (2.0 ** -e), e, False
+def _propagate(X, E, x, logs):
+    """X <- exp(-x H) X for H = diag(E), one column at a time.
+
+    Column c is X applied to basis vector c and its nonzero rows lie in one
+    invariant subspace.  The factor exp(-x s_c), with s_c the lowest energy
+    among the column's nonzero rows, is taken out and added to the column's
+    log scale, so the remaining factors exp(-x (E_i - s_c)) are <= 1 with the
+    largest equal to 1: no column underflows as a whole, however far above
+    the ground state its subspace lies."""
+    live = X != 0
+    s = np.min(np.where(live, E[:, None], np.inf), axis=0)
+    s = np.where(np.isfinite(s), s, 0.0)
+    arg = np.where(live, -x * (E[:, None] - s[None, :]), -np.inf)
+    return np.exp(arg) * X, logs - x * s
+
+
+def _rescale(X, logs):
+    """Divide every column by a power of two (exact) so that its largest
+    modulus lies in [1/2, 1); the factor goes into the column's log scale."""
+    m = np.max(np.abs(X), axis=0)
+    e = np.where(m > 0, np.frexp(m)[1], 0)
+    return X * np.ldexp(1.0, -e)[None, :], logs + e * LN2
+
+
+def _close(X, logs):
+    """Tr of the column-scaled X as (mantissa, log_scale)."""
+    d = np.diagonal(X)
+    live = d != 0
+    if not np.any(live):
+        return 0.0, 0.0
+    lmax = float(np.max(logs[live]))
+    tr = np.sum(d[live] * np.exp(logs[live] - lmax))
+    return (complex(tr) if np.iscomplexobj(tr) else float(tr)), lmax
+
+
+def _chain(X, E, ops, tau, beta):
+    """Apply the time-ordered string to X (columns = start basis vectors)."""
+    logs = np.zeros(X.shape[1])
+    prev = 0.0
+    for t, O in zip(tau, ops):
+        X, logs = _propagate(X, E, float(t) - prev, logs)
+        X = O @ X
+        X, logs = _rescale(X, logs)
+        prev = float(t)
+    X, logs = _propagate(X, E, beta - prev, logs)
+    return _close(X, logs)
 
 
 class DenseTrace:
@@ -54,10 +125,10 @@ class DenseTrace:
         self.imp = imp
         self.nf = imp.n_flavors
         self.beta = float(imp.beta)
-        H = hamiltonian_dense(imp.h1, imp.U)
-        if not np.allclose(H, H.conj().T, atol=1e-12):
+        H = hamiltonian_sparse(imp.h1, imp.U)
+        if abs(H - H.conj().T).max() > 1e-12:
             raise ValueError("H_loc is not Hermitian")
-        self.E, self.V = scipy.linalg.eigh(H)
+        self.E, self.V = _eigh_keeping_zeros(H)
         self.E0 = float(self.E[0])
         self.dtype = self.V.dtype
         self._ops = {}
@@ -69,28 +140,11 @@ class DenseTrace:
             self._ops[code] = self.V.conj().T @ (C @ self.V)
         return self._ops[code]
 
-    def propagator(self, x: float) -> np.ndarray:
-        """Diagonal of exp(-x (H - E0)) in the eigenbasis."""
-        return np.exp(-x * (self.E - self.E0))
-
     def trace(self, tau, op):
         """(mantissa, log_scale) of w_loc for the time-ordered string (tau, op)."""
         tau, op = _check_string(tau, op, self.beta, self.nf)
         D = self.E.shape[0]
-        X = np.eye(D, dtype=self.dtype)
-        exp2 = 0
-        prev = 0.0
-        for t, o in zip(tau, op):
-            X = self.propagator(t - prev)[:, None] * X
-            X = self.op_matrix(int(o)) @ X
-            prev = float(t)
-            X, e, zero = _rescale(X)
-            if zero:
-                return 0.0, 0.0
-            exp2 += e
-        X = self.propagator(self.beta - prev)[:, None] * X
-        return complex(np.trace(X)) if np.iscomplexobj(X) else float(np.trace(X)), \
-            exp2 * LN2 - self.beta * self.E0
+        return _chain(np.eye(D, dtype=self.dtype), self.E, [self.op_matrix(int(o)) for o in op], tau, self.beta)
 
     def abs_scale(self, tau, op):
         """(mantissa, log_scale) of A = the same chain with every operator
@@ -99,23 +153,12 @@ class DenseTrace:
         evaluation scales with A, not with |w_loc|; when |w_loc| << A the
         trace is cancellation dominated."""
         tau, op = _check_string(tau, op, self.beta, self.nf)
-        X = np.eye(self.E.shape[0])
-        exp2 = 0
-        prev = 0.0
-        for t, o in zip(tau, op):
-            X = self.propagator(t - prev)[:, None] * X
-            X = np.abs(self.op_matrix(int(o))) @ X
-            prev = float(t)
-            X, e, zero = _rescale(X)
-            if zero:
-                return 0.0, 0.0
-            exp2 += e
-        X = self.propagator(self.beta - prev)[:, None] * X
-        return float(np.trace(X)), exp2 * LN2 - self.beta * self.E0
+        D = self.E.shape[0]
+        return _chain(np.eye(D), self.E, [np.abs(self.op_matrix(int(o))) for o in op], tau, self.beta)
 
     def partition_function(self):
         """Order zero: Z = Tr exp(-beta H) as (mantissa, log_scale)."""
-        return float(np.sum(self.propagator(self.beta))), -self.beta * self.E0
+        return float(np.sum(np.exp(-self.beta * (self.E - self.E0)))), -self.beta * self.E0
 
 
 def expm_trace(imp, tau, op):
@@ -128,16 +171,13 @@ def expm_trace(imp, tau, op):
     s = float(np.min(np.real(np.diag(H)) - off))
     Hs = H - s * np.eye(D)
     X = np.eye(D, dtype=H.dtype)
-    exp2 = 0
+    logs = np.zeros(D)
     prev = 0.0
     for t, o in zip(tau, op):
         X = scipy.linalg.expm(-(t - prev) * Hs) @ X
         X = operator(imp.n_flavors, int(o)) @ X
         prev = float(t)
-        X, e, zero = _rescale(X)
-        if zero:
-            return 0.0, 0.0
-        exp2 += e
+        X, logs = _rescale(X, logs)
     X = scipy.linalg.expm(-(imp.beta - prev) * Hs) @ X
-    tr = np.trace(X)
-    return (complex(tr) if np.iscomplexobj(X) else float(tr)), exp2 * LN2 - imp.beta * s
+    m, l = _close(X, logs)
+    return m, l - imp.beta * s
