@@ -1,0 +1,234 @@
+/*
+ * ctrace — CT-HYB local trace on one MI355X (gfx950), C ABI.
+ *
+ * What it computes (Sec. 2.2, the local weight w_loc, evaluated in the block
+ * form of Sec. 3.3.1):
+ *
+ *   w_loc(C) = Tr[ P(beta - tau_n) O_n P(tau_n - tau_{n-1}) ... O_1 P(tau_1) ]
+ *            = sum_{q0} Tr[ P(q0) F_n(q_{n-1}) ... P(q1) F_1(q0) P(q0) ],
+ *
+ * with P(x) = exp(-x H_loc) diagonal in the H_loc eigenbasis, O_j an
+ * annihilator or creator, F_alpha(q) its dense block from sector q to sector
+ * s_alpha(q), and the sum running over the start sectors q0 whose sector
+ * string q0 -> q1 -> ... returns to q0 without entering the zero sector.
+ * The time-ordering sign is not applied: the caller passes the operators
+ * already in time order, as in the naive form of Sec. 3.3.1.
+ *
+ * Conventions used by every entry point
+ *  - Operator code: op = 2*flavor + dagger (dagger = 1 for c+).  op[0] at
+ *    tau[0] acts first (rightmost factor).  tau is non-decreasing in
+ *    [0, beta); equal times are applied in array order.
+ *  - Values: trace = (re + i*im) * exp(log_scale).  The split between
+ *    mantissa and scale is not unique; compare values, not fields.
+ *  - Streams: all device work is enqueued on the hipStream_t given to
+ *    ctr_create.  Host-pointer entry points return after the result is on
+ *    the host; *_device entry points only enqueue.
+ *  - Memory: the library never allocates device memory.  Everything it
+ *    keeps (operator blocks, tables, per-call scratch) is carved out of the
+ *    arena the caller passes to ctr_create (pre-allocated device pool, as in
+ *    Sec. 3.3.2).  Running out of arena returns CTR_ERR_OOM and leaves the
+ *    context usable.
+ *  - Threads: a context is not thread safe; use one per host thread.
+ *  - Errors: no exceptions cross the ABI; ctr_last_error gives detail.
+ */
+#ifndef CTRACE_H
+#define CTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTR_ABI_VERSION 1
+
+typedef enum {
+  CTR_OK = 0,
+  CTR_ERR_ARG = -1,         /* bad pointer, size or table content */
+  CTR_ERR_OOM = -2,         /* arena too small for this call (context still usable) */
+  CTR_ERR_DEVICE = -3,      /* a HIP runtime call failed */
+  CTR_ERR_UNSORTED = -4,    /* tau not non-decreasing */
+  CTR_ERR_RANGE = -5,       /* tau outside [0, beta) or operator code out of range */
+  CTR_ERR_STATE = -6,       /* call needs ctr_set_impurity first */
+  CTR_ERR_UNSUPPORTED = -7  /* impurity or option outside what the kernels handle */
+} ctr_status;
+
+/* ctr_opts.precision */
+enum { CTR_FP64 = 0, CTR_FP32_SPLIT = 1 };
+
+/* ctr_value.flags bits */
+enum {
+  CTR_FLAG_ZERO = 1,      /* no sector string survives: the trace is exactly 0 */
+  CTR_FLAG_REJECTED = 2,  /* lazy call: bound below threshold, trace not evaluated */
+  CTR_FLAG_INVALID = 4    /* device-input call: this configuration failed validation */
+};
+
+typedef struct ctr_ctx ctr_ctx;
+
+typedef struct {
+  double re, im;       /* mantissa of the trace (im = 0 for real impurities) */
+  double log_scale;    /* trace = (re + i im) * exp(log_scale) */
+  double log_bound;    /* log of the lazy upper bound on |trace| (same units);
+                          -inf when no string survives */
+  int32_t n_strings;   /* number of surviving sector strings */
+  int32_t flags;       /* CTR_FLAG_* */
+} ctr_value;
+
+typedef struct {
+  int32_t precision;   /* CTR_FP64 (default) or CTR_FP32_SPLIT */
+  int32_t slices;      /* CTR_FP32_SPLIT: slices per operand, 0 = library default */
+  int32_t reserved[2]; /* must be 0 */
+} ctr_opts;
+
+/*
+ * The impurity in sector form (Sec. 3.3.1): sector dimensions, the H_loc
+ * eigenvalues of every sector, the sector map s_alpha(q) and the annihilator
+ * blocks in the eigenbases.
+ *
+ *  beta          inverse temperature (> 0)
+ *  n_flavors     number of flavors (1..32); operator codes run over 2*n_flavors
+ *  n_sectors     number of sectors
+ *  is_complex    0: blocks are float64; 1: blocks are complex128 (interleaved re, im)
+ *  sector_dim    [n_sectors] sector dimensions (>= 1)
+ *  energies      [sum(sector_dim)] eigenvalues, sector after sector, each
+ *                sector ascending; unshifted (the library subtracts the global
+ *                minimum and folds it into log_scale)
+ *  next          [n_sectors * 2*n_flavors] row-major, next[q*2nf + op] = sector
+ *                reached from q by operator op, or -1 (zero sector).  Must be
+ *                consistent: next[q][2f+1] = p  <=>  next[p][2f] = q.
+ *  blocks        [n_sectors * n_flavors] pointers: blocks[q*nf + f] is the
+ *                annihilator block of flavor f leaving sector q, row-major
+ *                dim(next[q][2f]) x dim(q), element [m][n] = <m| c_f |n>
+ *                (reading of the index order of Sec. 3.3.1: output row first).
+ *                NULL iff next[q][2f] == -1.  Creator blocks are not passed:
+ *                the block of c+_f leaving q is the conjugate transpose of the
+ *                annihilator block leaving next[q][2f+1].
+ *  block_norm    optional [n_sectors * n_flavors] spectral norms of the blocks
+ *                (used by the lazy bound); NULL means 1, exact for every
+ *                nonzero block of c_f in an orthonormal eigenbasis.
+ */
+typedef struct {
+  double beta;
+  int32_t n_flavors;
+  int32_t n_sectors;
+  int32_t is_complex;
+  int32_t reserved;              /* must be 0 */
+  const int32_t *sector_dim;
+  const double *energies;
+  const int32_t *next;
+  const void *const *blocks;
+  const double *block_norm;
+} ctr_impurity;
+
+/* Library version string. */
+const char *ctr_version(void);
+
+/* Human-readable name of a status code. */
+const char *ctr_status_string(ctr_status s);
+
+/* Last error message of a context (empty string if none); valid until the
+ * next call on the context. */
+const char *ctr_last_error(const ctr_ctx *ctx);
+
+/*
+ * Create a context on HIP device `device`, sub-allocating from the caller's
+ * device arena [arena, arena + arena_bytes) (alignment 256 bytes; the caller
+ * keeps ownership and must keep it alive until ctr_destroy), enqueueing all
+ * work on `hip_stream` (a hipStream_t, or NULL for the null stream).
+ * Errors: CTR_ERR_ARG (null out/arena, arena < 1 MiB), CTR_ERR_DEVICE.
+ */
+ctr_status ctr_create(int device, void *arena, size_t arena_bytes, void *hip_stream, ctr_ctx **out);
+
+/* Destroy a context (NULL allowed).  Waits for the context's stream. */
+void ctr_destroy(ctr_ctx *ctx);
+
+/*
+ * Load an impurity: validates the tables, copies energies, tables and
+ * blocks to the arena in the kernels' layout (column-major, zero padded,
+ * creator blocks materialised, complex split into planes).  Host buffers
+ * are read during the call only.  Replaces any previous impurity and
+ * resets the arena.  Errors: CTR_ERR_ARG (inconsistent tables, missing
+ * block), CTR_ERR_OOM, CTR_ERR_UNSUPPORTED (largest sector beyond the
+ * kernels' limit), CTR_ERR_DEVICE.
+ */
+ctr_status ctr_set_impurity(ctr_ctx *ctx, const ctr_impurity *imp);
+
+/* Bytes of the arena in use by the loaded impurity. */
+size_t ctr_arena_resident_bytes(const ctr_ctx *ctx);
+
+/*
+ * One trace.  tau[n_ops], op[n_ops] are host arrays (n_ops may be 0: the
+ * partition function Z = Tr exp(-beta H)).  opts may be NULL (FP64).
+ * Errors: CTR_ERR_UNSORTED, CTR_ERR_RANGE, CTR_ERR_STATE, CTR_ERR_OOM,
+ * CTR_ERR_DEVICE.  A configuration none of whose strings survives returns
+ * CTR_OK with flags CTR_FLAG_ZERO and re = im = 0.
+ */
+ctr_status ctr_trace(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32_t *op,
+                     const ctr_opts *opts, ctr_value *out);
+
+/*
+ * n_cfg traces in one pass.  Configuration c is tau[offsets[c] ..
+ * offsets[c+1]), op[same]; offsets has n_cfg + 1 entries, offsets[0] = 0.
+ * All host arrays; out[n_cfg] host.  Large batches are split internally
+ * to fit the arena.  Errors as ctr_trace (the first invalid configuration
+ * fails the whole call before any device work).
+ */
+ctr_status ctr_trace_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau,
+                           const int32_t *op, const ctr_opts *opts, ctr_value *out);
+
+/*
+ * Same as ctr_trace_batch with every array already in device memory
+ * (d_offsets[n_cfg+1], d_tau, d_op, d_out[n_cfg]); only enqueues work on
+ * the context's stream.  Validation happens on the device: an invalid
+ * configuration gets CTR_FLAG_INVALID and re = im = 0.  Errors:
+ * CTR_ERR_OOM (per-call scratch does not fit; the call is split into
+ * chunks first, so this means even one configuration does not fit),
+ * CTR_ERR_STATE, CTR_ERR_DEVICE.
+ */
+ctr_status ctr_trace_batch_device(ctr_ctx *ctx, int32_t n_cfg, const int64_t *d_offsets,
+                                  const double *d_tau, const int32_t *d_op, const ctr_opts *opts,
+                                  ctr_value *d_out);
+
+/*
+ * Lazy traces (Sec. 3.3.1, lazy-trace bounds): per configuration, the
+ * upper bound B = sum_s rank_s * prod ||P|| * prod ||F|| (spectral norms,
+ * exact for the diagonal propagators) is computed first; if
+ * log(B) < log_threshold[c] the configuration is reported with
+ * CTR_FLAG_REJECTED and not evaluated, otherwise the exact trace is
+ * returned.  Host arrays as in ctr_trace_batch.
+ */
+ctr_status ctr_trace_lazy_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau,
+                                const int32_t *op, const double *log_threshold, const ctr_opts *opts,
+                                ctr_value *out);
+
+/* Log of the lazy upper bound on |trace| for one configuration (-inf if no
+ * string survives).  Host arrays. */
+ctr_status ctr_bound(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32_t *op, double *log_bound);
+
+/*
+ * Sector strings of one operator string (Sec. 3.3.1, the map s_alpha(q)):
+ * writes the start sectors q0 whose string survives, ascending, into
+ * q0_out[0 .. *n_out) (q0_out must hold n_sectors entries).  Computed by
+ * the same device kernel the traces use.
+ */
+ctr_status ctr_strings(ctr_ctx *ctx, int32_t n_ops, const int32_t *op, int32_t *q0_out, int32_t *n_out);
+
+/* Wait for all work enqueued by the context. */
+ctr_status ctr_synchronize(ctr_ctx *ctx);
+
+/*
+ * Instrumentation for roofline reports: when enabled (on != 0), every launch
+ * of the chain kernel (the block-product loop) is bracketed by HIP events
+ * recorded on the context's stream.  ctr_kernel_timing_read waits for the
+ * stream, returns the summed duration in milliseconds and the number of
+ * launches since the last read, and clears the record.
+ */
+ctr_status ctr_kernel_timing(ctr_ctx *ctx, int32_t on);
+ctr_status ctr_kernel_timing_read(ctr_ctx *ctx, double *total_ms, int32_t *n_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTRACE_H */

@@ -1,0 +1,554 @@
+// Host side of the C ABI declared in include/ctrace.h: context, arena
+// sub-allocation, impurity upload in the kernels' layout, validation,
+// batching into arena-sized chunks and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctrace_internal.h"
+
+using ctr::BatchArgs;
+using ctr::DevImp;
+using ctr::PanelRes;
+using ctr::StrRec;
+
+struct ctr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  size_t resident = 0;  // bytes of the arena held by the loaded impurity
+  bool loaded = false;
+  DevImp imp{};
+  int n_sec = 0, nf = 0, nops = 0, max_dim = 0;
+  double beta = 0.0;
+  long long max_panels_per_cfg = 0;
+  int grid = 0;
+  unsigned int* counter = nullptr;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+ctr_status fail(ctr_ctx* ctx, ctr_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+ctr_status hip_fail(ctr_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, CTR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                  \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+// Bump allocator over [base, end) of the arena.
+struct Bump {
+  char* base;
+  size_t off, cap;
+  void* take(size_t bytes) {
+    size_t o = align_up(off);
+    if (o + bytes > cap) return nullptr;
+    off = o + bytes;
+    return base + o;
+  }
+};
+
+// Host-side check of one configuration (host-pointer entry points).
+ctr_status check_config(ctr_ctx* ctx, long long n, const double* tau, const int32_t* op, long long cfg) {
+  if (n < 0 || n > ctr::kMaxOps)
+    return fail(ctx, CTR_ERR_ARG, "configuration " + std::to_string(cfg) + ": operator count outside [0, " +
+                                      std::to_string(ctr::kMaxOps) + "]");
+  for (long long i = 0; i < n; ++i) {
+    if (!(tau[i] >= 0.0 && tau[i] < ctx->beta))
+      return fail(ctx, CTR_ERR_RANGE, "configuration " + std::to_string(cfg) + ": tau outside [0, beta)");
+    if (op[i] < 0 || op[i] >= ctx->nops)
+      return fail(ctx, CTR_ERR_RANGE, "configuration " + std::to_string(cfg) + ": operator code out of range");
+    if (i > 0 && !(tau[i] >= tau[i - 1]))
+      return fail(ctx, CTR_ERR_UNSORTED, "configuration " + std::to_string(cfg) + ": tau not sorted");
+  }
+  return CTR_OK;
+}
+
+size_t scratch_per_cfg(const ctr_ctx* ctx) {
+  return (size_t)ctx->n_sec * sizeof(StrRec) + 3 * sizeof(int) + 2 * sizeof(double) + sizeof(long long) +
+         (size_t)ctx->max_panels_per_cfg * sizeof(PanelRes);
+}
+
+// Scratch for n_cfg configurations after `b`'s current offset.  Returns false if it does not fit.
+bool carve(ctr_ctx* ctx, Bump& b, int n_cfg, BatchArgs& a) {
+  a.n_cfg = n_cfg;
+  a.rec = (StrRec*)b.take((size_t)n_cfg * ctx->n_sec * sizeof(StrRec));
+  a.cfg_cnt = (int*)b.take((size_t)n_cfg * sizeof(int));
+  a.cfg_flags = (int*)b.take((size_t)n_cfg * sizeof(int));
+  a.cfg_nstr = (int*)b.take((size_t)n_cfg * sizeof(int));
+  a.cfg_logB = (double*)b.take((size_t)n_cfg * sizeof(double));
+  a.cfg_off = (long long*)b.take((size_t)(n_cfg + 1) * sizeof(long long));
+  a.res = (PanelRes*)b.take((size_t)n_cfg * ctx->max_panels_per_cfg * sizeof(PanelRes));
+  a.counter = ctx->counter;
+  return a.rec && a.cfg_cnt && a.cfg_flags && a.cfg_nstr && a.cfg_logB && a.cfg_off && a.res;
+}
+
+ctr_status enqueue(ctr_ctx* ctx, const BatchArgs& a, bool plan_only) {
+  hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
+  if (plan_only) return CTR_OK;
+  e = ctr::launch_scan(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "scan kernel");
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (ctx->timing) {
+    HIP_TRY(ctx, hipEventCreate(&t0));
+    HIP_TRY(ctx, hipEventCreate(&t1));
+    HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
+  }
+  e = ctr::launch_chain(ctx->imp, a, ctx->grid, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "chain kernel");
+  if (ctx->timing) {
+    HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
+    ctx->events.emplace_back(t0, t1);
+  }
+  e = ctr::launch_combine(ctx->imp, a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "combine kernel");
+  return CTR_OK;
+}
+
+ctr_status ready(ctr_ctx* ctx) {
+  if (!ctx) return CTR_ERR_ARG;
+  if (!ctx->loaded) return fail(ctx, CTR_ERR_STATE, "no impurity loaded");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  ctx->err.clear();
+  return CTR_OK;
+}
+
+ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts) {
+  if (!opts) return CTR_OK;
+  if (opts->reserved[0] || opts->reserved[1]) return fail(ctx, CTR_ERR_ARG, "ctr_opts.reserved must be 0");
+  if (opts->precision == CTR_FP64) return CTR_OK;
+  if (opts->precision == CTR_FP32_SPLIT)
+    return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT is not available in this build");
+  return fail(ctx, CTR_ERR_ARG, "unknown precision");
+}
+
+// Host-pointer batch: validates, then runs arena-sized chunks; `mode` 0 =
+// traces, 1 = bounds only (out_bound), thresholds optional.
+ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
+                      const double* log_thr, ctr_value* out, double* out_bound, int mode,
+                      BatchArgs* last = nullptr) {
+  if (n_cfg < 0 || (n_cfg > 0 && (!offsets || (!out && !out_bound))))
+    return fail(ctx, CTR_ERR_ARG, "null argument");
+  if (n_cfg == 0) return CTR_OK;
+  if (offsets[0] != 0) return fail(ctx, CTR_ERR_ARG, "offsets[0] must be 0");
+  for (int32_t c = 0; c < n_cfg; ++c) {
+    const long long n = offsets[c + 1] - offsets[c];
+    if (n > 0 && (!tau || !op)) return fail(ctx, CTR_ERR_ARG, "null tau/op");
+    ctr_status s = check_config(ctx, n, tau + offsets[c], op + offsets[c], c);
+    if (s != CTR_OK) return s;
+  }
+  const size_t per_cfg = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64;
+  int32_t c0 = 0;
+  std::vector<long long> offs;
+  while (c0 < n_cfg) {
+    // largest chunk that fits the free arena
+    const size_t free_bytes = ctx->arena_bytes - ctx->resident;
+    int32_t c1 = c0;
+    size_t need = 8 * kAlign;
+    while (c1 < n_cfg) {
+      const size_t more = per_cfg + (size_t)(offsets[c1 + 1] - offsets[c1]) * (sizeof(double) + sizeof(int32_t));
+      if (need + more > free_bytes) break;
+      need += more;
+      ++c1;
+    }
+    if (c1 == c0) return fail(ctx, CTR_ERR_OOM, "arena too small for one configuration");
+    const int32_t m = c1 - c0;
+    const long long ops0 = offsets[c0], nops = offsets[c1] - offsets[c0];
+    Bump b{ctx->arena, ctx->resident, ctx->arena_bytes};
+    BatchArgs a{};
+    long long* d_offs = (long long*)b.take((size_t)(m + 1) * sizeof(long long));
+    double* d_tau = (double*)b.take((size_t)std::max<long long>(nops, 1) * sizeof(double));
+    int* d_op = (int*)b.take((size_t)std::max<long long>(nops, 1) * sizeof(int));
+    ctr_value* d_out = (ctr_value*)b.take((size_t)m * sizeof(ctr_value));
+    double* d_thr = log_thr ? (double*)b.take((size_t)m * sizeof(double)) : nullptr;
+    if (!d_offs || !d_tau || !d_op || !d_out || (log_thr && !d_thr) || !carve(ctx, b, m, a))
+      return fail(ctx, CTR_ERR_OOM, "arena too small");
+    offs.resize(m + 1);
+    for (int32_t i = 0; i <= m; ++i) offs[i] = offsets[c0 + i] - ops0;
+    HIP_TRY(ctx, hipMemcpyAsync(d_offs, offs.data(), (m + 1) * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+    if (nops > 0) {
+      HIP_TRY(ctx, hipMemcpyAsync(d_tau, tau + ops0, nops * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(d_op, op + ops0, nops * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    }
+    if (d_thr) HIP_TRY(ctx, hipMemcpyAsync(d_thr, log_thr + c0, m * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    a.offsets = d_offs;
+    a.tau = d_tau;
+    a.op = d_op;
+    a.log_thr = d_thr;
+    a.out = d_out;
+    ctr_status s = enqueue(ctx, a, mode == 1);
+    if (s != CTR_OK) return s;
+    if (mode == 1) {
+      HIP_TRY(ctx, hipMemcpyAsync(out_bound + c0, a.cfg_logB, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+      HIP_TRY(ctx, hipMemcpyAsync(out + c0, d_out, m * sizeof(ctr_value), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (last) *last = a;
+    c0 = c1;
+  }
+  return CTR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctr_version(void) { return "ctrace 0.1 (gfx950, FP64 MFMA)"; }
+
+const char* ctr_status_string(ctr_status s) {
+  switch (s) {
+    case CTR_OK: return "CTR_OK";
+    case CTR_ERR_ARG: return "CTR_ERR_ARG";
+    case CTR_ERR_OOM: return "CTR_ERR_OOM";
+    case CTR_ERR_DEVICE: return "CTR_ERR_DEVICE";
+    case CTR_ERR_UNSORTED: return "CTR_ERR_UNSORTED";
+    case CTR_ERR_RANGE: return "CTR_ERR_RANGE";
+    case CTR_ERR_STATE: return "CTR_ERR_STATE";
+    case CTR_ERR_UNSUPPORTED: return "CTR_ERR_UNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+const char* ctr_last_error(const ctr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ctr_status ctr_create(int device, void* arena, size_t arena_bytes, void* hip_stream, ctr_ctx** out) {
+  if (!out || !arena) return CTR_ERR_ARG;
+  *out = nullptr;
+  if (arena_bytes < (1u << 20)) return CTR_ERR_ARG;
+  if (((uintptr_t)arena) % kAlign) return CTR_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return CTR_ERR_DEVICE;
+  ctr_ctx* ctx = new ctr_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->arena = (char*)arena;
+  ctx->arena_bytes = arena_bytes;
+  *out = ctx;
+  return CTR_OK;
+}
+
+void ctr_destroy(ctr_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& ev : ctx->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  delete ctx;
+}
+
+size_t ctr_arena_resident_bytes(const ctr_ctx* ctx) { return ctx ? ctx->resident : 0; }
+
+ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
+  if (!ctx) return CTR_ERR_ARG;
+  if (!imp) return fail(ctx, CTR_ERR_ARG, "null impurity");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->loaded = false;
+  ctx->resident = 0;
+  const int nf = imp->n_flavors, ns = imp->n_sectors, nops = 2 * nf;
+  if (!(imp->beta > 0.0) || nf < 1 || nf > 32 || ns < 1 || imp->reserved != 0)
+    return fail(ctx, CTR_ERR_ARG, "beta, n_flavors or n_sectors out of range");
+  if (!imp->sector_dim || !imp->energies || !imp->next || !imp->blocks)
+    return fail(ctx, CTR_ERR_ARG, "null table");
+  const bool cplx = imp->is_complex != 0;
+  std::vector<int> dim(imp->sector_dim, imp->sector_dim + ns);
+  int maxd = 0;
+  for (int q = 0; q < ns; ++q) {
+    if (dim[q] < 1) return fail(ctx, CTR_ERR_ARG, "sector dimension < 1");
+    maxd = std::max(maxd, dim[q]);
+  }
+  std::vector<int> next(imp->next, imp->next + (size_t)ns * nops);
+  for (int q = 0; q < ns; ++q)
+    for (int f = 0; f < nf; ++f) {
+      const int a = next[q * nops + 2 * f], c = next[q * nops + 2 * f + 1];
+      if (a < -1 || a >= ns || c < -1 || c >= ns) return fail(ctx, CTR_ERR_ARG, "next entry out of range");
+      if ((a >= 0) != (imp->blocks[q * nf + f] != nullptr))
+        return fail(ctx, CTR_ERR_ARG, "block presence does not match next[q][2f]");
+      if (a >= 0 && next[a * nops + 2 * f + 1] != q)
+        return fail(ctx, CTR_ERR_ARG, "next table: c_f then c+_f does not return to the sector");
+      if (c >= 0 && next[c * nops + 2 * f] != q)
+        return fail(ctx, CTR_ERR_ARG, "next table: c+_f then c_f does not return to the sector");
+    }
+  if (maxd > ctr::chain_max_rows(cplx))
+    return fail(ctx, CTR_ERR_UNSUPPORTED, "largest sector (" + std::to_string(maxd) +
+                                              ") exceeds the LDS-resident chain kernel limit of " +
+                                              std::to_string(ctr::chain_max_rows(cplx)));
+
+  // energies: global minimum, per-sector minimum, shifted and padded copies
+  std::vector<double> emin(ns), esh;
+  std::vector<int> eoff(ns);
+  double E0 = INFINITY;
+  {
+    long long p = 0;
+    for (int q = 0; q < ns; ++q) {
+      double m = INFINITY;
+      for (int i = 0; i < dim[q]; ++i) {
+        const double e = imp->energies[p + i];
+        if (!std::isfinite(e)) return fail(ctx, CTR_ERR_ARG, "non-finite energy");
+        m = std::min(m, e);
+      }
+      emin[q] = m;
+      E0 = std::min(E0, m);
+      eoff[q] = (int)esh.size();
+      for (int i = 0; i < ctr::pad16(dim[q]); ++i) esh.push_back(i < dim[q] ? imp->energies[p + i] - m : 0.0);
+      p += dim[q];
+    }
+  }
+  std::vector<double> lognorm((size_t)ns * nops, 0.0);
+  if (imp->block_norm)
+    for (int q = 0; q < ns; ++q)
+      for (int f = 0; f < nf; ++f) {
+        const double v = imp->block_norm[q * nf + f];
+        if (next[q * nops + 2 * f] >= 0) {
+          if (!(v > 0.0)) return fail(ctx, CTR_ERR_ARG, "block_norm must be > 0");
+          lognorm[q * nops + 2 * f] = std::log(v);
+          // c+_f leaving p = next[q][2f] is the adjoint of this block: same norm
+          lognorm[next[q * nops + 2 * f] * nops + 2 * f + 1] = std::log(v);
+        }
+      }
+
+  // block layout
+  std::vector<long long> boff((size_t)ns * nops, -1);
+  long long pool_doubles = 0;
+  for (int q = 0; q < ns; ++q)
+    for (int o = 0; o < nops; ++o) {
+      const int t = next[q * nops + o];
+      if (t < 0) continue;
+      boff[q * nops + o] = pool_doubles;
+      const long long sz = (long long)ctr::pad16(dim[t]) * ctr::pad4(dim[q]) * (cplx ? 2 : 1);
+      pool_doubles += (sz + 31) & ~31LL;
+    }
+
+  Bump b{ctx->arena, 0, ctx->arena_bytes};
+  ctx->counter = (unsigned int*)b.take(sizeof(unsigned int));
+  int* d_dim = (int*)b.take(ns * sizeof(int));
+  int* d_next = (int*)b.take((size_t)ns * nops * sizeof(int));
+  long long* d_boff = (long long*)b.take((size_t)ns * nops * sizeof(long long));
+  double* d_emin = (double*)b.take(ns * sizeof(double));
+  int* d_eoff = (int*)b.take(ns * sizeof(int));
+  double* d_esh = (double*)b.take(esh.size() * sizeof(double));
+  double* d_lognorm = (double*)b.take((size_t)ns * nops * sizeof(double));
+  double* d_pool = (double*)b.take((size_t)std::max(pool_doubles, 1LL) * sizeof(double));
+  if (!ctx->counter || !d_dim || !d_next || !d_boff || !d_emin || !d_eoff || !d_esh || !d_lognorm || !d_pool)
+    return fail(ctx, CTR_ERR_OOM, "arena too small for the impurity (" +
+                                      std::to_string((pool_doubles * 8) >> 20) + " MiB of blocks)");
+  HIP_TRY(ctx, hipMemcpyAsync(d_dim, dim.data(), ns * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_next, next.data(), next.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_boff, boff.data(), boff.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_emin, emin.data(), ns * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_eoff, eoff.data(), ns * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_esh, esh.data(), esh.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_lognorm, lognorm.data(), lognorm.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+
+  // blocks: column-major, zero padded; creators are conjugate transposes of
+  // the annihilator block leaving the target sector
+  std::vector<double> stage;
+  for (int q = 0; q < ns; ++q)
+    for (int o = 0; o < nops; ++o) {
+      const int t = next[q * nops + o];
+      if (t < 0) continue;
+      const int f = o >> 1, dag = o & 1;
+      const int d_out = dim[t], d_in = dim[q];
+      const int ld = ctr::pad16(d_out), kp = ctr::pad4(d_in);
+      const size_t plane = (size_t)ld * kp;
+      stage.assign(plane * (cplx ? 2 : 1), 0.0);
+      if (!dag) {
+        // annihilator leaving q: host block row-major d_out x d_in
+        const void* src = imp->blocks[q * nf + f];
+        for (int m = 0; m < d_out; ++m)
+          for (int k = 0; k < d_in; ++k) {
+            const size_t h = (size_t)m * d_in + k, dst = (size_t)k * ld + m;
+            if (cplx) {
+              const double* z = (const double*)src + 2 * h;
+              stage[dst] = z[0];
+              stage[plane + dst] = z[1];
+            } else {
+              stage[dst] = ((const double*)src)[h];
+            }
+          }
+      } else {
+        // creator leaving q = adjoint of the annihilator leaving t (d_in x d_out row-major)
+        const void* src = imp->blocks[t * nf + f];
+        for (int k = 0; k < d_in; ++k)
+          for (int m = 0; m < d_out; ++m) {
+            const size_t h = (size_t)k * d_out + m, dst = (size_t)k * ld + m;
+            if (cplx) {
+              const double* z = (const double*)src + 2 * h;
+              stage[dst] = z[0];
+              stage[plane + dst] = -z[1];
+            } else {
+              stage[dst] = ((const double*)src)[h];
+            }
+          }
+      }
+      HIP_TRY(ctx, hipMemcpyAsync(d_pool + boff[q * nops + o], stage.data(), stage.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+
+  ctx->imp.n_sec = ns;
+  ctx->imp.nops = nops;
+  ctx->imp.is_complex = cplx ? 1 : 0;
+  ctx->imp.xrows = ctr::pad16(maxd);
+  ctx->imp.beta = imp->beta;
+  ctx->imp.E0 = E0;
+  ctx->imp.dim = d_dim;
+  ctx->imp.next = d_next;
+  ctx->imp.boff = d_boff;
+  ctx->imp.emin = d_emin;
+  ctx->imp.eoff = d_eoff;
+  ctx->imp.esh = d_esh;
+  ctx->imp.lognorm = d_lognorm;
+  ctx->imp.pool = d_pool;
+  ctx->n_sec = ns;
+  ctx->nf = nf;
+  ctx->nops = nops;
+  ctx->max_dim = maxd;
+  ctx->beta = imp->beta;
+  long long mp = 0;
+  for (int q = 0; q < ns; ++q) mp += (dim[q] + ctr::kPanel - 1) / ctr::kPanel;
+  ctx->max_panels_per_cfg = mp;
+  size_t lds = 0;
+  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, &lds);
+  if (ctx->grid <= 0)
+    return fail(ctx, CTR_ERR_UNSUPPORTED, "chain kernel does not fit the device (LDS " + std::to_string(lds) + " B)");
+  ctx->resident = align_up(b.off);
+  ctx->loaded = true;
+  return CTR_OK;
+}
+
+ctr_status ctr_trace_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
+                           const ctr_opts* opts, ctr_value* out) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
+  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0);
+}
+
+ctr_status ctr_trace(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, const ctr_opts* opts,
+                     ctr_value* out) {
+  if (n_ops < 0) return fail(ctx, CTR_ERR_ARG, "n_ops < 0");
+  const int64_t offs[2] = {0, n_ops};
+  return ctr_trace_batch(ctx, 1, offs, tau, op, opts, out);
+}
+
+ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau,
+                                const int32_t* op, const double* log_threshold, const ctr_opts* opts,
+                                ctr_value* out) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
+  if (n_cfg > 0 && !log_threshold) return fail(ctx, CTR_ERR_ARG, "null log_threshold");
+  return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0);
+}
+
+ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double* log_bound) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if (!log_bound || n_ops < 0) return fail(ctx, CTR_ERR_ARG, "bad argument");
+  const int64_t offs[2] = {0, n_ops};
+  return host_batch(ctx, 1, offs, tau, op, nullptr, nullptr, log_bound, 1);
+}
+
+ctr_status ctr_strings(ctr_ctx* ctx, int32_t n_ops, const int32_t* op, int32_t* q0_out, int32_t* n_out) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if (!q0_out || !n_out || n_ops < 0 || (n_ops > 0 && !op)) return fail(ctx, CTR_ERR_ARG, "bad argument");
+  std::vector<double> tau((size_t)std::max(n_ops, 1), 0.0);
+  const int64_t offs[2] = {0, n_ops};
+  double lb = 0.0;
+  BatchArgs a{};
+  if ((s = host_batch(ctx, 1, offs, tau.data(), op, nullptr, nullptr, &lb, 1, &a)) != CTR_OK) return s;
+  std::vector<StrRec> rec(ctx->n_sec);
+  HIP_TRY(ctx, hipMemcpyAsync(rec.data(), a.rec, rec.size() * sizeof(StrRec), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  int k = 0;
+  for (int q = 0; q < ctx->n_sec; ++q)
+    if (rec[q].n_panels > 0) q0_out[k++] = q;
+  *n_out = k;
+  return CTR_OK;
+}
+
+ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_offsets, const double* d_tau,
+                                  const int32_t* d_op, const ctr_opts* opts, ctr_value* d_out) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
+  if (n_cfg < 0 || (n_cfg > 0 && (!d_offsets || !d_out))) return fail(ctx, CTR_ERR_ARG, "null argument");
+  const size_t free_bytes = ctx->arena_bytes - ctx->resident;
+  const size_t per_cfg = scratch_per_cfg(ctx) + 64;
+  const long long fit = (long long)((free_bytes > 8 * kAlign ? free_bytes - 8 * kAlign : 0) / per_cfg);
+  if (n_cfg > 0 && fit < 1) return fail(ctx, CTR_ERR_OOM, "arena too small for one configuration");
+  for (int32_t c0 = 0; c0 < n_cfg;) {
+    const int32_t m = (int32_t)std::min<long long>(fit, n_cfg - c0);
+    Bump b{ctx->arena, ctx->resident, ctx->arena_bytes};
+    BatchArgs a{};
+    if (!carve(ctx, b, m, a)) return fail(ctx, CTR_ERR_OOM, "arena too small");
+    a.offsets = (const long long*)d_offsets + c0;
+    a.tau = d_tau;
+    a.op = d_op;
+    a.log_thr = nullptr;
+    a.out = d_out + c0;
+    if ((s = enqueue(ctx, a, false)) != CTR_OK) return s;
+    c0 += m;
+  }
+  return CTR_OK;
+}
+
+ctr_status ctr_kernel_timing(ctr_ctx* ctx, int32_t on) {
+  if (!ctx) return CTR_ERR_ARG;
+  ctx->timing = on != 0;
+  return CTR_OK;
+}
+
+ctr_status ctr_kernel_timing_read(ctr_ctx* ctx, double* total_ms, int32_t* n_launches) {
+  if (!ctx || !total_ms || !n_launches) return CTR_ERR_ARG;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double sum = 0.0;
+  for (auto& ev : ctx->events) {
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.first, ev.second));
+    sum += ms;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  *total_ms = sum;
+  *n_launches = (int32_t)ctx->events.size();
+  ctx->events.clear();
+  return CTR_OK;
+}
+
+ctr_status ctr_synchronize(ctr_ctx* ctx) {
+  if (!ctx) return CTR_ERR_ARG;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CTR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal data structures shared by the host side of the C ABI and the
+// gfx950 kernels.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ctrace.h"
+
+namespace ctr {
+
+constexpr int kPanel = 16;        // columns of the carried matrix per work item (one MFMA tile)
+constexpr int kMaxOps = 1024;     // operators per configuration held in LDS by the plan kernel
+constexpr int kPlanThreads = 256;
+
+inline int pad16(int x) { return (x + 15) & ~15; }
+inline int pad4(int x) { return (x + 3) & ~3; }
+
+// Impurity as resident in the arena (all pointers are device addresses).
+struct DevImp {
+  int n_sec;
+  int nops;          // 2 * n_flavors
+  int is_complex;
+  int xrows;         // pad16(largest sector dimension)
+  double beta;
+  double E0;         // global lowest eigenvalue
+  const int* dim;            // [n_sec]
+  const int* next;           // [n_sec * nops]
+  const long long* boff;     // [n_sec * nops] offset (in doubles) of block (q, op) in pool, -1 if none
+  const double* emin;        // [n_sec] lowest eigenvalue of every sector
+  const int* eoff;           // [n_sec] offset of the sector's energies in esh
+  const double* esh;         // energies minus the sector's lowest one, zero padded to pad16(dim)
+  const double* lognorm;     // [n_sec * nops] log spectral norm of every block (0 when unknown)
+  const double* pool;        // operator blocks
+};
+// Block (q, op) with d_out = dim[next[q][op]], d_in = dim[q] is stored column-major:
+// element (row m, column k) at pool[boff + k * pad16(d_out) + m], columns padded to pad4(d_in),
+// zero padding; a complex block keeps its imaginary plane right after the real one.
+
+// One (configuration, start sector) string after the walk.
+struct StrRec {
+  int q_start;     // sector at the rotated start position
+  int jstar;       // rotated start position (index of the first operator applied)
+  int width;       // dimension of the start sector (columns of the carried matrix)
+  int n_panels;    // ceil(width / kPanel) if the string survives, else 0
+  int loc_off;     // panel offset of this string inside its configuration
+  int pad;
+  double L;        // sum over positions of dt * (lowest energy of the sector - E0)
+  double logB;     // log of the lazy bound of this string (without the -beta*E0 part)
+};
+
+struct PanelRes {
+  double re, im;   // mantissa
+  double e2;       // power-of-two exponent: panel contribution = (re + i im) * 2^e2 * exp(-L)
+};
+
+struct BatchArgs {
+  int n_cfg;
+  int pad;
+  const long long* offsets;  // [n_cfg + 1] absolute indices into tau / op
+  const double* tau;
+  const int* op;
+  const double* log_thr;     // [n_cfg] lazy thresholds or nullptr
+  StrRec* rec;               // [n_cfg * n_sec]
+  int* cfg_cnt;              // [n_cfg] panels per configuration
+  int* cfg_flags;            // [n_cfg]
+  int* cfg_nstr;             // [n_cfg]
+  double* cfg_logB;          // [n_cfg]
+  long long* cfg_off;        // [n_cfg + 1]
+  PanelRes* res;             // [total panels]
+  unsigned int* counter;     // persistent-kernel work counter
+  ctr_value* out;            // [n_cfg]
+};
+
+// Launchers (ctrace_kernels.hip).  All enqueue on `stream`.
+hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
+hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
+hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream);
+hipError_t launch_combine(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
+// LDS bytes and persistent grid size of the chain kernel for this impurity; grid 0 = unsupported.
+int chain_grid(const DevImp& imp, int device, size_t* lds_bytes);
+size_t chain_lds_bytes(const DevImp& imp);
+int chain_max_rows(int is_complex);
+
+}  // namespace ctr

@@ -1,0 +1,331 @@
+"""Python binding of libctrace (include/ctrace.h): argument marshalling only.
+
+Every entry point of the C ABI is exposed under the same name; the
+`TraceContext` class bundles the context with a device arena and stream
+taken from PyTorch (PyTorch is used for device memory and streams only).
+The library must be built (paper_2010_08482_amd.build_lib); importing this
+module without it raises immediately - there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libctrace.so")
+
+CTR_OK = 0
+CTR_FP64 = 0
+CTR_FP32_SPLIT = 1
+CTR_FLAG_ZERO = 1
+CTR_FLAG_REJECTED = 2
+CTR_FLAG_INVALID = 4
+
+
+class ctr_value(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double), ("log_scale", ctypes.c_double),
+                ("log_bound", ctypes.c_double), ("n_strings", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class ctr_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("slices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class ctr_impurity(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("n_flavors", ctypes.c_int32), ("n_sectors", ctypes.c_int32),
+                ("is_complex", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sector_dim", ctypes.POINTER(ctypes.c_int32)), ("energies", ctypes.POINTER(ctypes.c_double)),
+                ("next", ctypes.POINTER(ctypes.c_int32)), ("blocks", ctypes.POINTER(ctypes.c_void_p)),
+                ("block_norm", ctypes.POINTER(ctypes.c_double))]
+
+
+VALUE_DTYPE = np.dtype([("re", "<f8"), ("im", "<f8"), ("log_scale", "<f8"), ("log_bound", "<f8"),
+                        ("n_strings", "<i4"), ("flags", "<i4")])
+assert VALUE_DTYPE.itemsize == ctypes.sizeof(ctr_value)
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2010_08482_amd.build_lib` "
+                          "(the trace has no CPU or PyTorch fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ctr_version": (ctypes.c_char_p, []),
+        "ctr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "ctr_last_error": (ctypes.c_char_p, [vp]),
+        "ctr_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_size_t, vp, P(vp)]),
+        "ctr_destroy": (None, [vp]),
+        "ctr_set_impurity": (ctypes.c_int, [vp, P(ctr_impurity)]),
+        "ctr_arena_resident_bytes": (ctypes.c_size_t, [vp]),
+        "ctr_trace": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(ctr_opts), P(ctr_value)]),
+        "ctr_trace_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(ctr_opts), P(ctr_value)]),
+        "ctr_trace_batch_device": (ctypes.c_int, [vp, i32, vp, vp, vp, P(ctr_opts), vp]),
+        "ctr_trace_lazy_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(f64), P(ctr_opts),
+                                                P(ctr_value)]),
+        "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
+        "ctr_strings": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32)]),
+        "ctr_synchronize": (ctypes.c_int, [vp]),
+        "ctr_kernel_timing": (ctypes.c_int, [vp, i32]),
+        "ctr_kernel_timing_read": (ctypes.c_int, [vp, P(f64), P(i32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class CtraceError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{ctr_status_string(status)}: {msg}")
+        self.status = status
+
+
+def ctr_version() -> str:
+    return _lib.ctr_version().decode()
+
+
+def ctr_status_string(status: int) -> str:
+    return _lib.ctr_status_string(status).decode()
+
+
+def ctr_last_error(ctx) -> str:
+    return _lib.ctr_last_error(ctx).decode()
+
+
+def _check(ctx, status):
+    if status != CTR_OK:
+        raise CtraceError(status, ctr_last_error(ctx) if ctx else "")
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def ctr_create(device: int, arena_ptr: int, arena_bytes: int, stream_ptr: int):
+    out = ctypes.c_void_p()
+    st = _lib.ctr_create(int(device), ctypes.c_void_p(arena_ptr), ctypes.c_size_t(arena_bytes),
+                         ctypes.c_void_p(stream_ptr), ctypes.byref(out))
+    if st != CTR_OK:
+        raise CtraceError(st, "ctr_create failed")
+    return out
+
+
+def ctr_destroy(ctx) -> None:
+    _lib.ctr_destroy(ctx)
+
+
+def _opts(precision):
+    o = ctr_opts()
+    o.precision = int(precision)
+    return o
+
+
+def ctr_set_impurity(ctx, table) -> None:
+    """table: a SectorTable (dims, energies, next, blocks, beta, n_flavors, is_complex)."""
+    nf, ns = int(table.n_flavors), int(table.n_sectors)
+    dims = np.ascontiguousarray(table.dims, dtype=np.int32)
+    energies = np.ascontiguousarray(np.concatenate(table.energies), dtype=np.float64)
+    nxt = np.ascontiguousarray(table.next, dtype=np.int32).reshape(-1)
+    cdt = np.complex128 if table.is_complex else np.float64
+    keep = []
+    ptrs = (ctypes.c_void_p * (ns * nf))()
+    for q in range(ns):
+        for f in range(nf):
+            B = table.blocks[q][f]
+            if B is None:
+                ptrs[q * nf + f] = None
+            else:
+                arr = np.ascontiguousarray(B, dtype=cdt)
+                keep.append(arr)
+                ptrs[q * nf + f] = arr.ctypes.data
+    imp = ctr_impurity()
+    imp.beta = float(table.beta)
+    imp.n_flavors = nf
+    imp.n_sectors = ns
+    imp.is_complex = 1 if table.is_complex else 0
+    imp.reserved = 0
+    imp.sector_dim = _ptr(dims, ctypes.c_int32)
+    imp.energies = _ptr(energies, ctypes.c_double)
+    imp.next = _ptr(nxt, ctypes.c_int32)
+    imp.blocks = ptrs
+    imp.block_norm = None
+    _check(ctx, _lib.ctr_set_impurity(ctx, ctypes.byref(imp)))
+
+
+def ctr_arena_resident_bytes(ctx) -> int:
+    return int(_lib.ctr_arena_resident_bytes(ctx))
+
+
+def _string_arrays(tau, op):
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    op = np.ascontiguousarray(op, dtype=np.int32)
+    if tau.shape != op.shape:
+        raise ValueError("tau and op differ in length")
+    return tau, op
+
+
+def ctr_trace(ctx, tau, op, precision=CTR_FP64):
+    tau, op = _string_arrays(tau, op)
+    v = ctr_value()
+    o = _opts(precision)
+    _check(ctx, _lib.ctr_trace(ctx, int(op.size), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
+                               ctypes.byref(o), ctypes.byref(v)))
+    return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
+
+
+def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    tau, op = _string_arrays(tau, op)
+    n = offsets.size - 1
+    out = np.zeros(n, dtype=VALUE_DTYPE)
+    o = _opts(precision)
+    _check(ctx, _lib.ctr_trace_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
+                                     _ptr(op, ctypes.c_int32), ctypes.byref(o),
+                                     out.ctypes.data_as(ctypes.POINTER(ctr_value))))
+    return out
+
+
+def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64):
+    """Device pointers (ints); only enqueues on the context's stream."""
+    o = _opts(precision)
+    _check(ctx, _lib.ctr_trace_batch_device(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
+                                            ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
+                                            ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
+
+
+def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP64):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    tau, op = _string_arrays(tau, op)
+    thr = np.ascontiguousarray(log_threshold, dtype=np.float64)
+    n = offsets.size - 1
+    out = np.zeros(n, dtype=VALUE_DTYPE)
+    o = _opts(precision)
+    _check(ctx, _lib.ctr_trace_lazy_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
+                                          _ptr(op, ctypes.c_int32), _ptr(thr, ctypes.c_double), ctypes.byref(o),
+                                          out.ctypes.data_as(ctypes.POINTER(ctr_value))))
+    return out
+
+
+def ctr_bound(ctx, tau, op) -> float:
+    tau, op = _string_arrays(tau, op)
+    lb = ctypes.c_double()
+    _check(ctx, _lib.ctr_bound(ctx, int(op.size), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
+                               ctypes.byref(lb)))
+    return float(lb.value)
+
+
+def ctr_strings(ctx, op, n_sectors: int):
+    op = np.ascontiguousarray(op, dtype=np.int32)
+    q0 = np.zeros(max(n_sectors, 1), dtype=np.int32)
+    n = ctypes.c_int32()
+    _check(ctx, _lib.ctr_strings(ctx, int(op.size), _ptr(op, ctypes.c_int32), _ptr(q0, ctypes.c_int32),
+                                 ctypes.byref(n)))
+    return q0[: n.value].copy()
+
+
+def ctr_synchronize(ctx) -> None:
+    _check(ctx, _lib.ctr_synchronize(ctx))
+
+
+def ctr_kernel_timing(ctx, on: bool) -> None:
+    _check(ctx, _lib.ctr_kernel_timing(ctx, 1 if on else 0))
+
+
+def ctr_kernel_timing_read(ctx):
+    """(summed chain-kernel milliseconds, number of launches) since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int32()
+    _check(ctx, _lib.ctr_kernel_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
+
+
+def value_pair(v):
+    """(mantissa, log_scale) of a ctr_value record, complex mantissa if im != 0."""
+    m = complex(v["re"], v["im"]) if v["im"] != 0 else float(v["re"])
+    return m, float(v["log_scale"])
+
+
+class TraceContext:
+    """A ctrace context with its arena and stream taken from PyTorch."""
+
+    def __init__(self, table, arena_bytes: int | None = None, device: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the trace library runs on the GPU only")
+        self.device = int(device)
+        self.table = table
+        if arena_bytes is None:
+            arena_bytes = self.default_arena_bytes(table)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = ctr_create(self.device, self.arena.data_ptr(), self.arena.numel(), self.stream.cuda_stream)
+        ctr_set_impurity(self.ctx, table)
+
+    @staticmethod
+    def default_arena_bytes(table) -> int:
+        es = 16 if table.is_complex else 8
+        blocks = 0
+        d = np.asarray(table.dims)
+        for q in range(table.n_sectors):
+            for o in range(2 * table.n_flavors):
+                t = table.next[q, o]
+                if t >= 0:
+                    blocks += ((int(d[t]) + 15) // 16 * 16) * ((int(d[q]) + 3) // 4 * 4) * es + 256
+        return int(blocks + (256 << 20))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            ctr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def trace(self, tau, op, precision=CTR_FP64):
+        return ctr_trace(self.ctx, tau, op, precision)
+
+    def trace_batch(self, strings, precision=CTR_FP64):
+        """strings: sequence of (tau, op) pairs or objects with .tau and .op."""
+        taus = [np.asarray(getattr(s, "tau", s[0] if isinstance(s, tuple) else None), dtype=np.float64)
+                for s in strings]
+        ops = [np.asarray(getattr(s, "op", s[1] if isinstance(s, tuple) else None), dtype=np.int32)
+               for s in strings]
+        offs = np.zeros(len(strings) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([o.size for o in ops])
+        tau = np.concatenate(taus) if taus else np.zeros(0)
+        op = np.concatenate(ops) if ops else np.zeros(0, np.int32)
+        return ctr_trace_batch(self.ctx, offs, tau, op, precision)
+
+    def trace_packed(self, offsets, tau, op, precision=CTR_FP64):
+        return ctr_trace_batch(self.ctx, offsets, tau, op, precision)
+
+    def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64):
+        return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision)
+
+    def bound(self, tau, op) -> float:
+        return ctr_bound(self.ctx, tau, op)
+
+    def strings(self, op):
+        return ctr_strings(self.ctx, op, self.table.n_sectors)
+
+    def synchronize(self):
+        ctr_synchronize(self.ctx)
+
+
+def log_abs(v) -> float:
+    """log|trace| of a ctr_value record (-inf for zero)."""
+    a = math.hypot(float(v["re"]), float(v["im"]))
+    return math.log(a) + float(v["log_scale"]) if a > 0 else -math.inf

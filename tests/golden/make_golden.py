@@ -1,0 +1,78 @@
+"""Writes the stored expected values of the GPU parity tests.
+
+Calls only the CPU oracle (oracle/) and the seeded input generators
+(workloads/).  Each record: configuration index (or seed), operator count,
+oracle trace as (mantissa re, im, log_scale) and the cancellation scale A
+(sum of moduli of the Lehmann terms, same log units).
+
+    python tests/golden/make_golden.py [name ...]
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import DenseTrace  # noqa: E402
+from workloads import make_configs, make_impurity  # noqa: E402
+from workloads.configs import random_string  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def record(dt, idx, s):
+    m, l = dt.trace(s.tau, s.op)
+    a, la = dt.abs_scale(s.tau, s.op)
+    m = complex(m)
+    return {"i": int(idx), "n": int(s.n), "re": m.real, "im": m.imag, "log_scale": l, "abs": a, "abs_log": la}
+
+
+def config_set(name, impurity, config_id, count):
+    imp = make_impurity(impurity)
+    dt = DenseTrace(imp)
+    out = []
+    t0 = time.time()
+    for i, s in enumerate(make_configs(config_id, count)):
+        out.append(record(dt, i, s))
+        if (i + 1) % 25 == 0:
+            print(f"{name}: {i + 1}/{count} ({time.time() - t0:.0f}s)", flush=True)
+    return {"impurity": impurity, "config_id": config_id, "records": out}
+
+
+def random_set(name, impurity, seed, count, lo, hi):
+    imp = make_impurity(impurity)
+    dt = DenseTrace(imp)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        n = 2 * int(rng.integers(lo // 2, hi // 2 + 1))
+        s = random_string(rng, imp.n_flavors, imp.beta, n, "alternating")
+        r = record(dt, i, s)
+        r["tau"] = s.tau.tolist()
+        r["op"] = s.op.tolist()
+        out.append(r)
+    print(f"{name}: {count} done", flush=True)
+    return {"impurity": impurity, "seed": seed, "records": out}
+
+
+SETS = {
+    # d-shell workload strings (the benchmark's configurations), first 256
+    "dshell_config1": lambda: config_set("dshell_config1", "dshell", 1, 256),
+    # complex impurities small enough for the dense oracle
+    "pshell_random": lambda: random_set("pshell_random", "pshell", 77, 120, 2, 60),
+    "pshell_cf_random": lambda: random_set("pshell_cf_random", "pshell_cf", 78, 120, 2, 60),
+    "dshell_so_random": lambda: random_set("dshell_so_random", "dshell_so", 79, 80, 2, 80),
+}
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(SETS)
+    for name in names:
+        data = SETS[name]()
+        with open(os.path.join(HERE, name + ".json"), "w") as fh:
+            json.dump(data, fh, indent=0)
+        print("wrote", name, flush=True)

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every symbol the header declares.
+CPU only: no call that needs a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctrace.h")
+LIB = os.path.join(ROOT, "paper_2010_08482_amd", "libctrace.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("ctr_create", "ctr_destroy", "ctr_set_impurity", "ctr_trace", "ctr_trace_batch",
+                 "ctr_trace_batch_device", "ctr_trace_lazy_batch", "ctr_bound", "ctr_strings",
+                 "ctr_status_string", "ctr_last_error", "ctr_version", "ctr_synchronize",
+                 "ctr_arena_resident_bytes"):
+        assert want in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libctrace.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libctrace.so not built")
+def test_status_strings_and_argument_errors_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.ctr_status_string.restype = ctypes.c_char_p
+    assert lib.ctr_status_string(0) == b"CTR_OK"
+    assert lib.ctr_status_string(-2) == b"CTR_ERR_OOM"
+    lib.ctr_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.ctr_version()
+    # null output pointer is rejected before any device call
+    lib.ctr_create.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.ctr_create(0, None, 0, None, None) == -1
+
+
+def test_binding_names_match_header():
+    src = open(os.path.join(ROOT, "paper_2010_08482_amd", "ctrace.py")).read()
+    for name in declared_functions():
+        assert f"def {name}(" in src, name

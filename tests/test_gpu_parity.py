@@ -1,0 +1,357 @@
+"""GPU parity of the trace library against the CPU oracle, through the C ABI.
+
+Every comparison uses the parity bar of tests/tracecmp.close_enough:
+|gpu - oracle| <= 1e-10 |oracle|, or, for cancellation-dominated traces,
+<= 1e-12 A with A the sum of moduli of the Lehmann terms.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests.tracecmp import close_enough, rel_err
+from workloads import make_configs, make_impurity
+from workloads.configs import pack, random_string
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2010_08482_amd import ctrace
+
+    return ctrace
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    from paper_2010_08482_amd.sectors import build_sectors
+
+    cache = {}
+
+    def get(name, phase_seed=None, arena_bytes=None):
+        key = (name, phase_seed, arena_bytes)
+        if key not in cache:
+            say(f"[setup] sectors + ctr_set_impurity: {name} phase_seed={phase_seed} arena={arena_bytes}")
+            tab = build_sectors(make_impurity(name), phase_seed=phase_seed)
+            cache[key] = (tab, lib.TraceContext(tab, arena_bytes=arena_bytes))
+        return cache[key]
+
+    yield get
+    for _, c in cache.values():
+        c.close()
+
+
+def pair(v):
+    m = complex(v["re"], v["im"])
+    return (m if m.imag != 0 else m.real), float(v["log_scale"])
+
+
+def load_golden(name):
+    with open(os.path.join(HERE, "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+def golden_pair(r):
+    return complex(r["re"], r["im"]), r["log_scale"]
+
+
+def check_against(out, refs, scales, label):
+    bad = []
+    worst = 0.0
+    for i, (v, ref, sc) in enumerate(zip(out, refs, scales)):
+        got = pair(v)
+        if ref[0] == 0:
+            assert got[0] == 0 or (v["flags"] & 1), f"{label} #{i}: oracle zero, gpu {got}"
+            continue
+        if not close_enough(got, ref, sc):
+            bad.append((i, rel_err(got, ref)))
+        worst = max(worst, rel_err(got, ref))
+    say(f"{label}: {len(out)} traces, worst rel err {worst:.2e}, failures {bad[:5]}")
+    assert not bad
+
+
+# ---------------------------------------------------------------------------
+# order zero and the 16-state atom
+# ---------------------------------------------------------------------------
+
+def test_partition_function_closed_form(ctx):
+    tab, c = ctx("kanamori2")
+    say("[gpu] ctr_trace n=0 kanamori2")
+    v = c.trace([], [])
+    b = 10.0
+    z = (2 * math.exp(-7 * b) + 8 * math.exp(-2.25 * b) + 3 + 2 * math.exp(-b) + math.exp(-2 * b)), 7 * b
+    assert rel_err(pair(v), z) < 1e-13
+    assert v["n_strings"] == tab.n_sectors
+
+
+def test_config0_all_1000_vs_oracle(ctx):
+    from oracle import DenseTrace
+
+    tab, c = ctx("kanamori2")
+    imp = make_impurity("kanamori2")
+    dt = DenseTrace(imp)
+    cfgs = make_configs(0)
+    say("[gpu] ctr_trace_batch config0 x1000")
+    out = c.trace_batch(cfgs)
+    refs = [dt.trace(s.tau, s.op) for s in cfgs]
+    scales = [dt.abs_scale(s.tau, s.op) for s in cfgs]
+    check_against(out, refs, scales, "config0")
+    # the zero-string set: no survivor <=> CTR_FLAG_ZERO
+    for v, s in zip(out, cfgs):
+        assert bool(v["flags"] & 1) == (v["n_strings"] == 0)
+
+
+def _label_walk_check(ctx, name, cfgs):
+    from oracle.labels import label_table, label_walk
+
+    tab, c = ctx(name)
+    imp = make_impurity(name)
+    table = label_table(imp)
+    labels = [tuple(int(x) for x in row) for row in tab.labels]
+    for i, s in enumerate(cfgs):
+        got = sorted(labels[q] for q in c.strings(s.op))
+        want = sorted(label_walk(imp, s.op, table))
+        assert got == want, f"{name} #{i}"
+
+
+def test_strings_match_oracle_label_walk_config0(ctx):
+    say("[gpu] ctr_strings config0 x1000")
+    _label_walk_check(ctx, "kanamori2", make_configs(0))
+
+
+def test_strings_match_oracle_label_walk_config1(ctx):
+    say("[gpu] ctr_strings config1 x150")
+    _label_walk_check(ctx, "dshell", make_configs(1, 150))
+
+
+# ---------------------------------------------------------------------------
+# d-shell workload at full size (the benchmark's batch and launch path)
+# ---------------------------------------------------------------------------
+
+def _device_batch(lib, c, strings):
+    import torch
+
+    offs, tau, op = pack(strings)
+    dev = f"cuda:{c.device}"
+    d_offs = torch.from_numpy(offs).to(dev)
+    d_tau = torch.from_numpy(tau).to(dev)
+    d_op = torch.from_numpy(op).to(dev)
+    d_out = torch.zeros(len(strings) * lib.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    lib.ctr_trace_batch_device(c.ctx, len(strings), d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
+                               d_out.data_ptr())
+    c.synchronize()
+    return np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=lib.VALUE_DTYPE)
+
+
+def test_config1_full_batch_device_path_vs_golden(lib, ctx):
+    tab, c = ctx("dshell")
+    g = load_golden("dshell_config1")
+    cfgs = make_configs(1)
+    assert len(cfgs) == 10_000
+    say("[gpu] ctr_trace_batch_device config1 x10000")
+    out = _device_batch(lib, c, cfgs)
+    k = len(g["records"])
+    check_against(out[:k], [golden_pair(r) for r in g["records"]],
+                  [(r["abs"], r["abs_log"]) for r in g["records"]], "config1 golden (full-size batch)")
+    assert np.all(np.isfinite(out["re"])) and np.all(np.isfinite(out["log_scale"]))
+    assert not np.any(out["flags"] & 4)
+    # every value is below its own lazy bound
+    la = np.array([math.log(math.hypot(v["re"], v["im"])) + v["log_scale"] if (v["re"] or v["im"]) else -np.inf
+                   for v in out])
+    assert np.all(la <= out["log_bound"] + 1e-9)
+    # the host-pointer path agrees bit for bit
+    say("[gpu] ctr_trace_batch config1 x300 host path")
+    host = c.trace_batch(cfgs[:300])
+    assert np.array_equal(host["re"], out["re"][:300]) and np.array_equal(host["log_scale"], out["log_scale"][:300])
+
+
+@pytest.mark.parametrize("name", ["pshell_random", "pshell_cf_random", "dshell_so_random"])
+def test_complex_impurities_vs_golden(ctx, name):
+    g = load_golden(name)
+    tab, c = ctx(g["impurity"])
+    assert tab.is_complex
+    strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
+    say(f"[gpu] ctr_trace_batch {name} x{len(strings)}")
+    out = c.trace_batch(strings)
+    check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                  name)
+
+
+# ---------------------------------------------------------------------------
+# full f-shell size: density-density impurity, exact by state enumeration
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("phase_seed", [None, 5])
+def test_fshell_size_density_density_vs_enumeration(ctx, phase_seed):
+    from oracle import densdens_trace
+
+    tab, c = ctx("dd_fshell", phase_seed)
+    assert tab.max_dim == 327 and tab.is_complex == (phase_seed is not None)
+    imp = make_impurity("dd_fshell")
+    cfgs = make_configs(2, 48)  # 14 flavors, beta 40, orders 40..160
+    say(f"[gpu] ctr_trace_batch dd_fshell phase={phase_seed} x{len(cfgs)}")
+    out = c.trace_batch(cfgs)
+    refs = [densdens_trace(imp, s.tau, s.op) for s in cfgs]
+    scales = [densdens_trace(imp, s.tau, s.op, moduli=True) for s in cfgs]
+    check_against(out, refs, scales, f"dd_fshell phase={phase_seed}")
+    assert sum(1 for r in refs if r[0] != 0) >= 10
+
+
+def test_fshell_gauge_invariance(ctx):
+    _, cg = ctx("fshell")
+    _, cr = ctx("fshell_real")
+    cfgs = make_configs(2, 40)
+    say("[gpu] ctr_trace_batch fshell (complex) vs fshell_real x40")
+    a, b = cg.trace_batch(cfgs), cr.trace_batch(cfgs)
+    n_nz = 0
+    for i, (x, y) in enumerate(zip(a, b)):
+        if y["re"] == 0:
+            continue
+        n_nz += 1
+        assert rel_err(pair(x), pair(y)) < 1e-9, i
+    assert n_nz >= 10
+
+
+# ---------------------------------------------------------------------------
+# identities at d-shell size
+# ---------------------------------------------------------------------------
+
+def test_cyclicity_and_anticommutation_dshell(ctx):
+    from tests.tracecmp import add, insert_ops
+
+    tab, c = ctx("dshell")
+    rng = np.random.Generator(np.random.PCG64(3))
+    beta = tab.beta
+    say("[gpu] cyclicity / anticommutation dshell")
+    for i in range(20):
+        s = random_string(rng, 10, beta, 2 * int(rng.integers(5, 30)), "alternating")
+        w = pair(c.trace(s.tau, s.op))
+        d = float(rng.uniform(0, beta))
+        t2 = (s.tau + d) % beta
+        o = np.argsort(t2, kind="stable")
+        w2 = pair(c.trace(t2[o], s.op[o]))
+        if w[0] != 0:
+            assert rel_err(w2, w) < 1e-9, i
+        t_new = float(rng.uniform(0, beta))
+        f = int(rng.integers(10))
+        a = pair(c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f + 1, 2 * f])))
+        b = pair(c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f, 2 * f + 1])))
+        if w[0] != 0:
+            assert rel_err(add(a, b), w) < 1e-9, i
+
+
+# ---------------------------------------------------------------------------
+# edge cases, errors, arena, determinism, lazy bounds
+# ---------------------------------------------------------------------------
+
+def test_error_paths(lib, ctx):
+    tab, c = ctx("dshell")
+    say("[gpu] error paths")
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace([1.0, 0.5], [0, 1])
+    assert e.value.status == -4
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace([0.5, 1.0], [0, 99])
+    assert e.value.status == -5
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace([0.5, tab.beta], [0, 1])
+    assert e.value.status == -5
+    v = c.trace([0.5], [1])                       # odd: no string survives
+    assert v["flags"] & 1 and v["re"] == 0 and v["n_strings"] == 0
+    v = c.trace([0.5, 0.6], [1, 1])              # c+ c+ of one flavor: zero
+    assert v["flags"] & 1
+    assert c.trace_batch([]).shape == (0,)
+    v = c.trace([0.7, 0.7], [2 * 3 + 1, 2 * 3])  # equal times, c c+: allowed
+    assert v["n_strings"] > 0
+
+
+def test_device_path_flags_invalid_configuration(lib, ctx):
+    tab, c = ctx("dshell")
+    good = make_configs(1, 3)
+    bad = (np.array([2.0, 1.0]), np.array([0, 1], dtype=np.int32))
+    from workloads.configs import OperatorString
+
+    strings = [good[0], OperatorString(*bad), good[1], good[2]]
+    say("[gpu] device path with one unsorted configuration")
+    out = _device_batch(lib, c, strings)
+    ref = c.trace_batch([good[0], good[1], good[2]])
+    assert out[1]["flags"] & 4 and out[1]["re"] == 0
+    assert np.array_equal(out[[0, 2, 3]]["re"], ref["re"])
+
+
+def test_arena_oom_then_chunked_batches_identical(lib, ctx):
+    tab, big = ctx("dshell")
+    cfgs = make_configs(1, 300)
+    say("[gpu] small-arena chunking dshell x300")
+    ref = big.trace_batch(cfgs)
+    resident = lib.ctr_arena_resident_bytes(big.ctx)
+    with pytest.raises(lib.CtraceError) as e:
+        lib.TraceContext(tab, arena_bytes=max(1 << 20, resident // 2))
+    assert e.value.status == -2
+    small = lib.TraceContext(tab, arena_bytes=resident + (1 << 20))
+    try:
+        out = small.trace_batch(cfgs)  # ~5 KiB of scratch per configuration: several chunks
+        assert np.array_equal(out["re"], ref["re"]) and np.array_equal(out["log_scale"], ref["log_scale"])
+    finally:
+        small.close()
+
+
+def test_determinism_and_batch_order(ctx):
+    tab, c = ctx("dshell")
+    cfgs = make_configs(1, 400)
+    say("[gpu] determinism dshell x400")
+    a = c.trace_batch(cfgs)
+    b = c.trace_batch(cfgs)
+    r = c.trace_batch(cfgs[::-1])[::-1]
+    for x in (b, r):
+        assert np.array_equal(a["re"], x["re"]) and np.array_equal(a["im"], x["im"])
+        assert np.array_equal(a["log_scale"], x["log_scale"])
+
+
+def test_lazy_bound_and_rejection(lib, ctx):
+    tab, c = ctx("dshell")
+    cfgs = make_configs(1, 300)
+    offs, tau, op = pack(cfgs)
+    say("[gpu] lazy bounds dshell x300")
+    exact = c.trace_packed(offs, tau, op)
+    la = np.array([lib.log_abs(v) for v in exact])
+    lb = exact["log_bound"]
+    assert np.all(la <= lb + 1e-9)
+    # single-configuration bound call agrees with the batch field
+    assert abs(c.bound(cfgs[7].tau, cfgs[7].op) - lb[7]) < 1e-9
+    rng = np.random.Generator(np.random.PCG64(9))
+    thr = lb + rng.uniform(-3.0, 3.0, size=lb.size)
+    out = c.lazy_batch(offs, tau, op, thr)
+    rej = (out["flags"] & 2) != 0
+    assert np.array_equal(rej, (lb < thr) & (exact["n_strings"] > 0))
+    keep = ~rej
+    assert np.array_equal(out["re"][keep], exact["re"][keep])
+    assert np.array_equal(out["log_scale"][keep], exact["log_scale"][keep])
+    # no false rejection: a rejected trace is truly below its threshold
+    assert np.all(la[rej] < thr[rej])
+
+
+def test_blocks_beyond_lds_limit_are_reported(lib, ctx):
+    from paper_2010_08482_amd.sectors import build_sectors
+
+    tab = build_sectors(make_impurity("dd_fshell_n"))
+    assert tab.max_dim == 3432
+    say("[gpu] ctr_set_impurity with 3432-dim sectors")
+    with pytest.raises(lib.CtraceError) as e:
+        lib.TraceContext(tab, arena_bytes=1 << 30)
+    assert e.value.status == -7
