@@ -42,8 +42,10 @@ def _energies(imp) -> np.ndarray:
     return E
 
 
-def densdens_trace(imp, tau, op):
-    """(mantissa, log_scale) of w_loc for a density-density impurity."""
+def densdens_trace(imp, tau, op, moduli=False):
+    """(mantissa, log_scale) of w_loc for a density-density impurity.  With
+    moduli=True the signs are dropped: the sum of |terms| (cancellation
+    scale)."""
     tau = np.asarray(tau, dtype=np.float64)
     op = np.asarray(op, dtype=np.int64)
     nf = imp.n_flavors
@@ -72,7 +74,8 @@ def densdens_trace(imp, tau, op):
     if not np.any(alive):
         return 0.0, 0.0
     m = float(np.max(logw[alive]))
-    total = float(np.sum(sign[alive] * np.exp(logw[alive] - m)))
+    sg = np.abs(sign[alive]) if moduli else sign[alive]
+    total = float(np.sum(sg * np.exp(logw[alive] - m)))
     return total, m
 
 
