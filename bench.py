@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-sample", type=int, default=200)
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32-split leg")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy this many MiB once with a plain device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run here has a single MI355X and the trace path has no "
@@ -126,10 +129,17 @@ def main():
     d_out = torch.zeros(n_cfg * ctrace.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    def step():
+    def step(precision=ctrace.CTR_FP64, out_buf=None):
         ctrace.ctr_trace_batch_device(ctx.ctx, n_cfg, d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
-                                      d_out.data_ptr())
+                                      (out_buf if out_buf is not None else d_out).data_ptr(), precision)
 
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -147,7 +157,44 @@ def main():
     print(f"[bench] {args.steps} steps in {elapsed:.3f}s; chain kernel {chain_ms / max(launches, 1):.3f} ms "
           f"per launch over {launches} launches", file=sys.stderr, flush=True)
 
+    split = None
+    if not args.no_split:
+        # FP32-split leg: same batch, block products on FP32 MFMA over exact 8-bit slices
+        d_out_s = torch.zeros_like(d_out)
+        step(ctrace.CTR_FP32_SPLIT, d_out_s)
+        torch.cuda.synchronize()
+        ctrace.ctr_kernel_timing(ctx.ctx, True)
+        ctrace.ctr_kernel_timing_read(ctx.ctx)
+        ks = max(2, args.steps // 4)
+        ts = time.perf_counter()
+        for _ in range(ks):
+            step(ctrace.CTR_FP32_SPLIT, d_out_s)
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - ts
+        ms_s, n_s = ctrace.ctr_kernel_timing_read(ctx.ctx)
+        ctrace.ctr_kernel_timing(ctx.ctx, False)
+        outs = np.frombuffer(d_out_s.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)
+        rel_s = []
+        for a, b in zip(outs, out):
+            if b["re"] == 0 and b["im"] == 0:
+                continue
+            M = max(a["log_scale"], b["log_scale"])
+            x = complex(a["re"], a["im"]) * math.exp(a["log_scale"] - M)
+            y = complex(b["re"], b["im"]) * math.exp(b["log_scale"] - M)
+            rel_s.append(abs(x - y) / abs(y))
+        rel_s = np.array(rel_s)
+        split = {"value": n_cfg * ks / el_s, "unit": "trace evals/s", "steps": ks, "ms_per_step": el_s / ks * 1e3,
+                 "slice_bits": 8, "slices": 6, "fp32_products_per_fma": 21,
+                 "launch_ms": ms_s / max(n_s, 1),
+                 "rel_err_vs_fp64": {"p50": float(np.percentile(rel_s, 50)), "p99": float(np.percentile(rel_s, 99)),
+                                     "max": float(rel_s.max())} if rel_s.size else None}
+
     flops = algorithmic_flops(tab, strings)
+    if split is not None and split["launch_ms"] > 0:
+        per = flops / (split["launch_ms"] * 1e-3) / 1e12 / max(launches / max(args.steps, 1), 1)
+        split["achieved_fp64_equivalent_tflops"] = per
+        split["executed_fp32_tflops"] = 21 * per
+        split["frac_fp32_peak"] = 21 * per / 157.3
     per_launch_ms = chain_ms / max(launches, 1)
     launches_per_step = launches / max(args.steps, 1)
     achieved = flops / launches_per_step / (per_launch_ms * 1e-3) / 1e12 if per_launch_ms > 0 else None
@@ -204,7 +251,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "entry": "ctr_trace (one configuration, host pointers)"},
         "max_rel_err_vs_oracle_sample": rel,
-        "fp32_split": None,
+        "fp32_split": split,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -158,8 +158,8 @@ ctr_status ctr_set_impurity(ctr_ctx *ctx, const ctr_impurity *imp);
 size_t ctr_arena_resident_bytes(const ctr_ctx *ctx);
 
 /*
- * One trace.  tau[n_ops], op[n_ops] are host arrays (n_ops may be 0: the
- * partition function Z = Tr exp(-beta H)).  opts may be NULL (FP64).
+ * One trace.  tau[n_ops], op[n_ops] are host arrays (0 <= n_ops <= 512; 0
+ * gives the partition function Z = Tr exp(-beta H)).  opts may be NULL (FP64).
  * Errors: CTR_ERR_UNSORTED, CTR_ERR_RANGE, CTR_ERR_STATE, CTR_ERR_OOM,
  * CTR_ERR_DEVICE.  A configuration none of whose strings survives returns
  * CTR_OK with flags CTR_FLAG_ZERO and re = im = 0.

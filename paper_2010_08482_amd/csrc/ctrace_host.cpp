@@ -31,6 +31,8 @@ struct ctr_ctx {
   double beta = 0.0;
   long long max_panels_per_cfg = 0;
   int grid = 0;
+  int grid_split = 0;
+  int grid_wave = 0;  // > 0: FP64 traces use the wavefront-per-panel kernel (panels of 8 columns)
   unsigned int* counter = nullptr;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -86,6 +88,7 @@ ctr_status check_config(ctr_ctx* ctx, long long n, const double* tau, const int3
 }
 
 size_t scratch_per_cfg(const ctr_ctx* ctx) {
+  // panels counted with the narrowest panel width any kernel uses (upper bound)
   return (size_t)ctx->n_sec * sizeof(StrRec) + 3 * sizeof(int) + 2 * sizeof(double) + sizeof(long long) +
          (size_t)ctx->max_panels_per_cfg * sizeof(PanelRes);
 }
@@ -104,7 +107,9 @@ bool carve(ctr_ctx* ctx, Bump& b, int n_cfg, BatchArgs& a) {
   return a.rec && a.cfg_cnt && a.cfg_flags && a.cfg_nstr && a.cfg_logB && a.cfg_off && a.res;
 }
 
-ctr_status enqueue(ctr_ctx* ctx, const BatchArgs& a, bool plan_only) {
+ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split) {
+  const bool wave = !split && ctx->grid_wave > 0;
+  a.panel = wave ? ctr::kWavePanelHost : ctr::kPanel;
   hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
   if (plan_only) return CTR_OK;
@@ -116,7 +121,8 @@ ctr_status enqueue(ctr_ctx* ctx, const BatchArgs& a, bool plan_only) {
     HIP_TRY(ctx, hipEventCreate(&t1));
     HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
   }
-  e = ctr::launch_chain(ctx->imp, a, ctx->grid, ctx->stream);
+  e = wave ? ctr::launch_chain_wave(ctx->imp, a, ctx->grid_wave, ctx->stream)
+           : ctr::launch_chain(ctx->imp, a, split, split ? ctx->grid_split : ctx->grid, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "chain kernel");
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
@@ -135,19 +141,25 @@ ctr_status ready(ctr_ctx* ctx) {
   return CTR_OK;
 }
 
-ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts) {
+ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split) {
+  *split = false;
   if (!opts) return CTR_OK;
   if (opts->reserved[0] || opts->reserved[1]) return fail(ctx, CTR_ERR_ARG, "ctr_opts.reserved must be 0");
   if (opts->precision == CTR_FP64) return CTR_OK;
-  if (opts->precision == CTR_FP32_SPLIT)
-    return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT is not available in this build");
+  if (opts->precision == CTR_FP32_SPLIT) {
+    if (opts->slices != 0 && opts->slices != 6)
+      return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT supports 6 slices of 8 bits (slices = 0 or 6)");
+    if (ctx->grid_split <= 0) return fail(ctx, CTR_ERR_UNSUPPORTED, "split kernel does not fit the device");
+    *split = true;
+    return CTR_OK;
+  }
   return fail(ctx, CTR_ERR_ARG, "unknown precision");
 }
 
 // Host-pointer batch: validates, then runs arena-sized chunks; `mode` 0 =
 // traces, 1 = bounds only (out_bound), thresholds optional.
 ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
-                      const double* log_thr, ctr_value* out, double* out_bound, int mode,
+                      const double* log_thr, ctr_value* out, double* out_bound, int mode, bool split,
                       BatchArgs* last = nullptr) {
   if (n_cfg < 0 || (n_cfg > 0 && (!offsets || (!out && !out_bound))))
     return fail(ctx, CTR_ERR_ARG, "null argument");
@@ -198,7 +210,7 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     a.op = d_op;
     a.log_thr = d_thr;
     a.out = d_out;
-    ctr_status s = enqueue(ctx, a, mode == 1);
+    ctr_status s = enqueue(ctx, a, mode == 1, split);
     if (s != CTR_OK) return s;
     if (mode == 1) {
       HIP_TRY(ctx, hipMemcpyAsync(out_bound + c0, a.cfg_logB, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -293,6 +305,7 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
       if (c >= 0 && next[c * nops + 2 * f] != q)
         return fail(ctx, CTR_ERR_ARG, "next table: c+_f then c_f does not return to the sector");
     }
+  if (ns > 32767) return fail(ctx, CTR_ERR_UNSUPPORTED, "more than 32767 sectors");
   if (maxd > ctr::chain_max_rows(cplx))
     return fail(ctx, CTR_ERR_UNSUPPORTED, "largest sector (" + std::to_string(maxd) +
                                               ") exceeds the LDS-resident chain kernel limit of " +
@@ -343,6 +356,18 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
       pool_doubles += (sz + 31) & ~31LL;
     }
 
+  // row exponents of every block (FP32-split scaling): pad16(d_out) int16 per block
+  std::vector<long long> roff((size_t)ns * nops, -1);
+  long long rexp_n = 0;
+  for (int q = 0; q < ns; ++q)
+    for (int o = 0; o < nops; ++o) {
+      const int t = next[q * nops + o];
+      if (t < 0) continue;
+      roff[q * nops + o] = rexp_n;
+      rexp_n += ctr::pad16(dim[t]);
+    }
+  std::vector<short> rexp((size_t)std::max(rexp_n, 1LL), 0);
+
   Bump b{ctx->arena, 0, ctx->arena_bytes};
   ctx->counter = (unsigned int*)b.take(sizeof(unsigned int));
   int* d_dim = (int*)b.take(ns * sizeof(int));
@@ -352,8 +377,11 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   int* d_eoff = (int*)b.take(ns * sizeof(int));
   double* d_esh = (double*)b.take(esh.size() * sizeof(double));
   double* d_lognorm = (double*)b.take((size_t)ns * nops * sizeof(double));
+  long long* d_roff = (long long*)b.take((size_t)ns * nops * sizeof(long long));
+  short* d_rexp = (short*)b.take(rexp.size() * sizeof(short));
   double* d_pool = (double*)b.take((size_t)std::max(pool_doubles, 1LL) * sizeof(double));
-  if (!ctx->counter || !d_dim || !d_next || !d_boff || !d_emin || !d_eoff || !d_esh || !d_lognorm || !d_pool)
+  if (!ctx->counter || !d_dim || !d_next || !d_boff || !d_emin || !d_eoff || !d_esh || !d_lognorm || !d_pool ||
+      !d_roff || !d_rexp)
     return fail(ctx, CTR_ERR_OOM, "arena too small for the impurity (" +
                                       std::to_string((pool_doubles * 8) >> 20) + " MiB of blocks)");
   HIP_TRY(ctx, hipMemcpyAsync(d_dim, dim.data(), ns * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
@@ -405,16 +433,29 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
             }
           }
       }
+      for (int m = 0; m < ld; ++m) {
+        double mx = 0.0;
+        for (int k = 0; k < kp; ++k) {
+          mx = std::max(mx, std::fabs(stage[(size_t)k * ld + m]));
+          if (cplx) mx = std::max(mx, std::fabs(stage[plane + (size_t)k * ld + m]));
+        }
+        int ex = 0;
+        if (mx > 0.0) std::frexp(mx, &ex);  // mx < 2^ex
+        rexp[roff[q * nops + o] + m] = (short)std::max(-30000, std::min(30000, ex));
+      }
       HIP_TRY(ctx, hipMemcpyAsync(d_pool + boff[q * nops + o], stage.data(), stage.size() * sizeof(double),
                                   hipMemcpyHostToDevice, ctx->stream));
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     }
+  HIP_TRY(ctx, hipMemcpyAsync(d_roff, roff.data(), roff.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_rexp, rexp.data(), rexp.size() * sizeof(short), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
   ctx->imp.n_sec = ns;
   ctx->imp.nops = nops;
   ctx->imp.is_complex = cplx ? 1 : 0;
   ctx->imp.xrows = ctr::pad16(maxd);
+  ctx->imp.next_lds = (ns * nops <= 16384 && ns < 32768) ? 1 : 0;
   ctx->imp.beta = imp->beta;
   ctx->imp.E0 = E0;
   ctx->imp.dim = d_dim;
@@ -425,16 +466,20 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->imp.esh = d_esh;
   ctx->imp.lognorm = d_lognorm;
   ctx->imp.pool = d_pool;
+  ctx->imp.roff = d_roff;
+  ctx->imp.rexp = d_rexp;
   ctx->n_sec = ns;
   ctx->nf = nf;
   ctx->nops = nops;
   ctx->max_dim = maxd;
   ctx->beta = imp->beta;
   long long mp = 0;
-  for (int q = 0; q < ns; ++q) mp += (dim[q] + ctr::kPanel - 1) / ctr::kPanel;
+  for (int q = 0; q < ns; ++q) mp += (dim[q] + ctr::kWavePanelHost - 1) / ctr::kWavePanelHost;
   ctx->max_panels_per_cfg = mp;
   size_t lds = 0;
-  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, &lds);
+  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, false, &lds);
+  ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, true, nullptr);
+  ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
   if (ctx->grid <= 0)
     return fail(ctx, CTR_ERR_UNSUPPORTED, "chain kernel does not fit the device (LDS " + std::to_string(lds) + " B)");
   ctx->resident = align_up(b.off);
@@ -446,8 +491,9 @@ ctr_status ctr_trace_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, 
                            const ctr_opts* opts, ctr_value* out) {
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
-  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
-  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0);
+  bool split = false;
+  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
+  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split);
 }
 
 ctr_status ctr_trace(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, const ctr_opts* opts,
@@ -462,9 +508,10 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offs
                                 ctr_value* out) {
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
-  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
+  bool split = false;
+  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
   if (n_cfg > 0 && !log_threshold) return fail(ctx, CTR_ERR_ARG, "null log_threshold");
-  return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0);
+  return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split);
 }
 
 ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double* log_bound) {
@@ -472,7 +519,7 @@ ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32
   if (s != CTR_OK) return s;
   if (!log_bound || n_ops < 0) return fail(ctx, CTR_ERR_ARG, "bad argument");
   const int64_t offs[2] = {0, n_ops};
-  return host_batch(ctx, 1, offs, tau, op, nullptr, nullptr, log_bound, 1);
+  return host_batch(ctx, 1, offs, tau, op, nullptr, nullptr, log_bound, 1, false);
 }
 
 ctr_status ctr_strings(ctr_ctx* ctx, int32_t n_ops, const int32_t* op, int32_t* q0_out, int32_t* n_out) {
@@ -483,7 +530,7 @@ ctr_status ctr_strings(ctr_ctx* ctx, int32_t n_ops, const int32_t* op, int32_t* 
   const int64_t offs[2] = {0, n_ops};
   double lb = 0.0;
   BatchArgs a{};
-  if ((s = host_batch(ctx, 1, offs, tau.data(), op, nullptr, nullptr, &lb, 1, &a)) != CTR_OK) return s;
+  if ((s = host_batch(ctx, 1, offs, tau.data(), op, nullptr, nullptr, &lb, 1, false, &a)) != CTR_OK) return s;
   std::vector<StrRec> rec(ctx->n_sec);
   HIP_TRY(ctx, hipMemcpyAsync(rec.data(), a.rec, rec.size() * sizeof(StrRec), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -498,7 +545,8 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
                                   const int32_t* d_op, const ctr_opts* opts, ctr_value* d_out) {
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
-  if ((s = check_opts(ctx, opts)) != CTR_OK) return s;
+  bool split = false;
+  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
   if (n_cfg < 0 || (n_cfg > 0 && (!d_offsets || !d_out))) return fail(ctx, CTR_ERR_ARG, "null argument");
   const size_t free_bytes = ctx->arena_bytes - ctx->resident;
   const size_t per_cfg = scratch_per_cfg(ctx) + 64;
@@ -514,7 +562,7 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
     a.op = d_op;
     a.log_thr = nullptr;
     a.out = d_out + c0;
-    if ((s = enqueue(ctx, a, false)) != CTR_OK) return s;
+    if ((s = enqueue(ctx, a, false, split)) != CTR_OK) return s;
     c0 += m;
   }
   return CTR_OK;

@@ -10,7 +10,7 @@
 namespace ctr {
 
 constexpr int kPanel = 16;        // columns of the carried matrix per work item (one MFMA tile)
-constexpr int kMaxOps = 1024;     // operators per configuration held in LDS by the plan kernel
+constexpr int kMaxOps = 512;      // operators per configuration (held in LDS by the kernels)
 constexpr int kPlanThreads = 256;
 
 inline int pad16(int x) { return (x + 15) & ~15; }
@@ -22,6 +22,8 @@ struct DevImp {
   int nops;          // 2 * n_flavors
   int is_complex;
   int xrows;         // pad16(largest sector dimension)
+  int next_lds;      // 1 if the chain kernel keeps the sector map in LDS
+  int pad_;
   double beta;
   double E0;         // global lowest eigenvalue
   const int* dim;            // [n_sec]
@@ -31,6 +33,8 @@ struct DevImp {
   const int* eoff;           // [n_sec] offset of the sector's energies in esh
   const double* esh;         // energies minus the sector's lowest one, zero padded to pad16(dim)
   const double* lognorm;     // [n_sec * nops] log spectral norm of every block (0 when unknown)
+  const long long* roff;     // [n_sec * nops] offset of the block's row exponents in rexp
+  const short* rexp;         // per block and padded row: e with max_k |F[m][k]| < 2^e (FP32-split scaling)
   const double* pool;        // operator blocks
 };
 // Block (q, op) with d_out = dim[next[q][op]], d_in = dim[q] is stored column-major:
@@ -42,7 +46,7 @@ struct StrRec {
   int q_start;     // sector at the rotated start position
   int jstar;       // rotated start position (index of the first operator applied)
   int width;       // dimension of the start sector (columns of the carried matrix)
-  int n_panels;    // ceil(width / kPanel) if the string survives, else 0
+  int n_panels;    // ceil(width / panel width) if the string survives, else 0
   int loc_off;     // panel offset of this string inside its configuration
   int pad;
   double L;        // sum over positions of dt * (lowest energy of the sector - E0)
@@ -56,7 +60,7 @@ struct PanelRes {
 
 struct BatchArgs {
   int n_cfg;
-  int pad;
+  int panel;                 // columns per work item (16 block kernel, 8 wavefront kernel)
   const long long* offsets;  // [n_cfg + 1] absolute indices into tau / op
   const double* tau;
   const int* op;
@@ -75,11 +79,15 @@ struct BatchArgs {
 // Launchers (ctrace_kernels.hip).  All enqueue on `stream`.
 hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
-hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream);
+hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream);
 hipError_t launch_combine(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 // LDS bytes and persistent grid size of the chain kernel for this impurity; grid 0 = unsupported.
-int chain_grid(const DevImp& imp, int device, size_t* lds_bytes);
+int chain_grid(const DevImp& imp, int device, bool split, size_t* lds_bytes);
 size_t chain_lds_bytes(const DevImp& imp);
 int chain_max_rows(int is_complex);
+// Wavefront-per-panel chain kernel (sectors of at most 128 states); grid 0 = not applicable.
+int wave_grid(const DevImp& imp, int device, size_t* lds_bytes);
+hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream);
+constexpr int kWavePanelHost = 8;
 
 }  // namespace ctr

@@ -10,7 +10,8 @@
 //              work from an atomic counter and runs the whole chain
 //              X <- F_op * P * X with X resident in LDS, the diagonal
 //              propagator fused into the epilogue of the previous step, FP64
-//              MFMA 16x16x4 block products, and a per-column power-of-two
+//              MFMA block products (16x16x4, or 4x4x4 on groups of four columns
+//              for panels of at most 12 columns), and a per-column power-of-two
 //              rescale from wavefront max-reductions; the last operator only
 //              contributes the diagonal of F * X.
 //   k_combine  one thread per configuration: merges the (mantissa, exponent)
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
         R.q_start = qbest;
         R.jstar = jstar;
         R.width = best;
-        R.n_panels = (best + kPanel - 1) / kPanel;
+        R.n_panels = (best + B.panel - 1) / B.panel;
         R.L = L;
         R.logB = log((double)best) - L + logn;
         my_panels += R.n_panels;
@@ -207,22 +208,341 @@ __global__ __launch_bounds__(1024) void k_scan(BatchArgs B) {
 // chain
 // ---------------------------------------------------------------------------
 template <bool CPLX, int NW>
-__host__ __device__ constexpr size_t chain_lds_doubles(int xr) {
-  return (size_t)(CPLX ? 2 : 1) * xr * kPanel + 2 * (size_t)xr + NW * kPanel + (CPLX ? 2 : 1) * NW * 64 + kPanel;
+__host__ __device__ constexpr size_t chain_lds_bytes_t(int xr, int n_sec, int next_entries) {
+  return 8 * ((size_t)(CPLX ? 2 : 1) * xr * kPanel + 2 * (size_t)xr + NW * kPanel + (CPLX ? 2 : 1) * NW * 64 +
+              kMaxOps) +
+         4 * (kPanel + 2 * (size_t)n_sec) + 2 * (2 * (size_t)kMaxOps + 2 + next_entries);
+}
+
+// One chain step for a panel of at most 12 columns: FP64 MFMA 4x4x4 with four
+// blocks stacked along the rows, so a 16-row tile times a group of 4 columns
+// is one instruction and only ceil(ncols/4) column groups are computed.
+// Lane l holds A[row l%16][k l/16] (as for 16x16x4), B[k l/16][col l%4] and
+// D[row 4*((l%16)/4) + l/16][col l%4].
+template <bool CPLX, int NW, int MAXT>
+__device__ __forceinline__ void step_narrow(int t, const double* __restrict__ Fr, const double* __restrict__ Fi,
+                                            int ld, int ntiles, int d_in, const double* pa, const double* pb,
+                                            double* Xr, double* Xi, double* cmax, int* colexp, int col0,
+                                            int ncols, int G, int lane, int wave, int tid) {
+  const int ln = lane & 15, lq = lane >> 4, l3 = lane & 3;
+  const int orow = 4 * (ln >> 2) + lq;
+  double acc_r[MAXT][3], acc_i[MAXT][3];
+#pragma unroll
+  for (int tt = 0; tt < MAXT; ++tt)
+#pragma unroll
+    for (int g = 0; g < 3; ++g) acc_r[tt][g] = acc_i[tt][g] = 0.0;
+  if (t == 0) {
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+      const int tile = wave + tt * NW;
+      if (tile < ntiles) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          const int c = g * 4 + l3;
+          if (g < G && c < ncols) {
+            const int k = col0 + c;
+            const long long a = (long long)k * ld + tile * 16 + orow;
+            const double p = pa[k];
+            acc_r[tt][g] = Fr[a] * p;
+            if (CPLX) acc_i[tt][g] = Fi[a] * p;
+          }
+        }
+      }
+    }
+  } else {
+    const int ksteps = (d_in + 3) >> 2;
+    for (int kc = 0; kc < ksteps; ++kc) {
+      const int krow = kc * 4 + lq;
+      double br[3], bi[3];
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        br[g] = (g < G) ? Xr[krow * kPanel + g * 4 + l3] : 0.0;
+        bi[g] = (CPLX && g < G) ? Xi[krow * kPanel + g * 4 + l3] : 0.0;
+      }
+#pragma unroll
+      for (int tt = 0; tt < MAXT; ++tt) {
+        const int tile = wave + tt * NW;
+        if (tile < ntiles) {
+          const long long a = (long long)krow * ld + tile * 16 + ln;
+          const double ar = Fr[a];
+          const double ai = CPLX ? Fi[a] : 0.0;
+#pragma unroll
+          for (int g = 0; g < 3; ++g) {
+            if (g < G) {
+              acc_r[tt][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar, br[g], acc_r[tt][g], 0, 0, 0);
+              if (CPLX) {
+                acc_r[tt][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai, bi[g], acc_r[tt][g], 0, 0, 0);
+                acc_i[tt][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar, bi[g], acc_i[tt][g], 0, 0, 0);
+                acc_i[tt][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai, br[g], acc_i[tt][g], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // X consumed by every wave; pb complete
+
+  double cm[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int tt = 0; tt < MAXT; ++tt) {
+    const int tile = wave + tt * NW;
+    if (tile < ntiles) {
+      const double p = pb[tile * 16 + orow];
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        acc_r[tt][g] *= p;
+        cm[g] = fmax(cm[g], fabs(acc_r[tt][g]));
+        if (CPLX) {
+          acc_i[tt][g] *= p;
+          cm[g] = fmax(cm[g], fabs(acc_i[tt][g]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    cm[g] = fmax(cm[g], __shfl_xor(cm[g], 4));
+    cm[g] = fmax(cm[g], __shfl_xor(cm[g], 8));
+    cm[g] = fmax(cm[g], __shfl_xor(cm[g], 16));
+    cm[g] = fmax(cm[g], __shfl_xor(cm[g], 32));
+  }
+  if (lane < 4) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      if (g < G) cmax[wave * kPanel + g * 4 + lane] = cm[g];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    if (g < G) {
+      double M = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) M = fmax(M, cmax[w2 * kPanel + g * 4 + l3]);
+      int e = 0;
+      if (M > 0.0) frexp(M, &e);
+      const double sc = ldexp(1.0, -e);
+      if (tid < 4) colexp[g * 4 + tid] += e;
+#pragma unroll
+      for (int tt = 0; tt < MAXT; ++tt) {
+        const int tile = wave + tt * NW;
+        if (tile < ntiles) {
+          const int m = tile * 16 + orow;
+          Xr[m * kPanel + g * 4 + l3] = acc_r[tt][g] * sc;
+          if (CPLX) Xi[m * kPanel + g * 4 + l3] = acc_i[tt][g] * sc;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// One chain step in FP32-split precision.  Every operand is cut into
+// kSlices integer-valued slices of kSliceBits bits (F per row, scaled by the
+// row's power of two; X per column, already in (-1, 1) after the rescale):
+//   f = sum_s A_s 2^{-b s},  x = sum_t B_t 2^{-b t},  |A_s|, |B_t| < 2^b.
+// The products A_s B_t with s + t <= kSlices + 1 run on FP32 MFMA 16x16x4.
+// Slice products are integers below 2^{2b}; with at most kSlices products per
+// level and split_chunk() values of k per chunk, every partial sum stays below
+// 2^24, so the FP32 accumulation is exact.  After each chunk the level sums
+// are converted to FP64 (exact) and added with their weights 2^{-b L}; the
+// eigenvalue propagators, the rescale and the final trace stay FP64.
+constexpr int kSliceBits = 8;
+constexpr int kSlices = 6;
+// values of k per exact chunk: 40 real, 20 complex (two products per slice pair)
+template <bool CPLX>
+__host__ __device__ constexpr int split_chunk() {
+  return ((1 << (24 - 2 * kSliceBits)) / (kSlices * (CPLX ? 2 : 1))) & ~3;
+}
+
+// D layout of the FP32 16x16x4 MFMA: item i of lane l is row f32_row(i, l/16), column l%16.
+__device__ __forceinline__ int f32_row(int i, int lq) { return 4 * lq + i; }
+
+__device__ __forceinline__ void slice_digits(double v, float* d) {
+#pragma unroll
+  for (int s = 0; s < kSlices; ++s) {
+    v *= (double)(1 << kSliceBits);
+    const double a = trunc(v);
+    d[s] = (float)a;
+    v -= a;
+  }
 }
 
 template <bool CPLX, int NW, int MAXT>
+__device__ __forceinline__ void step_split(int t, const double* __restrict__ Fr, const double* __restrict__ Fi,
+                                           const short* __restrict__ rexp, int ld, int ntiles, int d_in,
+                                           const double* pa, const double* pb, double* Xr, double* Xi,
+                                           double* cmax, int* colexp, int col0, int ncols, int lane, int wave,
+                                           int tid) {
+  typedef float flt4 __attribute__((ext_vector_type(4)));
+  const int ln = lane & 15, lq = lane >> 4;
+  double acc_r[MAXT][4], acc_i[MAXT][4];
+#pragma unroll
+  for (int tt = 0; tt < MAXT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc_r[tt][i] = acc_i[tt][i] = 0.0;
+
+  if (t == 0) {
+    // column-scaled copy of F (no product), already in the FP32 D layout
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+      const int tile = wave + tt * NW;
+      if (tile < ntiles && ln < ncols) {
+        const int k = col0 + ln;
+        const double p = pa[k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const long long a = (long long)k * ld + tile * 16 + f32_row(i, lq);
+          acc_r[tt][i] = Fr[a] * p;
+          if (CPLX) acc_i[tt][i] = Fi[a] * p;
+        }
+      }
+    }
+  } else {
+    // inverse row scale of the A rows this lane feeds (row tile*16 + ln)
+    double ainv[MAXT];
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+      const int tile = wave + tt * NW;
+      ainv[tt] = (tile < ntiles) ? ldexp(1.0, -(int)rexp[tile * 16 + ln]) : 0.0;
+    }
+    const int ksteps = (d_in + 3) >> 2;
+    for (int k0 = 0; k0 < ksteps; k0 += split_chunk<CPLX>() / 4) {
+      const int k1 = min(ksteps, k0 + split_chunk<CPLX>() / 4);
+      flt4 lr[MAXT][kSlices], li[MAXT][kSlices];
+#pragma unroll
+      for (int tt = 0; tt < MAXT; ++tt)
+#pragma unroll
+        for (int L = 0; L < kSlices; ++L) {
+          lr[tt][L] = flt4{0.f, 0.f, 0.f, 0.f};
+          li[tt][L] = flt4{0.f, 0.f, 0.f, 0.f};
+        }
+      for (int kc = k0; kc < k1; ++kc) {
+        const int krow = kc * 4 + lq;
+        float bxr[kSlices], bxi[kSlices];
+        slice_digits(Xr[krow * kPanel + ln], bxr);
+        if (CPLX) slice_digits(Xi[krow * kPanel + ln], bxi);
+#pragma unroll
+        for (int tt = 0; tt < MAXT; ++tt) {
+          const int tile = wave + tt * NW;
+          if (tile < ntiles) {
+            const long long a = (long long)krow * ld + tile * 16 + ln;
+            float afr[kSlices], afi[kSlices], afn[kSlices];
+            slice_digits(Fr[a] * ainv[tt], afr);
+            if (CPLX) {
+              slice_digits(Fi[a] * ainv[tt], afi);
+#pragma unroll
+              for (int s2 = 0; s2 < kSlices; ++s2) afn[s2] = -afi[s2];
+            }
+            // level L = s + t (slice indices from 1), kept for L <= kSlices + 1
+#pragma unroll
+            for (int L = 2; L <= kSlices + 1; ++L) {
+#pragma unroll
+              for (int s1 = 1; s1 < L; ++s1) {
+                const int t1 = L - s1;
+                lr[tt][L - 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s1 - 1], bxr[t1 - 1], lr[tt][L - 2], 0, 0, 0);
+                if (CPLX) {
+                  lr[tt][L - 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(afn[s1 - 1], bxi[t1 - 1], lr[tt][L - 2], 0, 0, 0);
+                  li[tt][L - 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s1 - 1], bxi[t1 - 1], li[tt][L - 2], 0, 0, 0);
+                  li[tt][L - 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(afi[s1 - 1], bxr[t1 - 1], li[tt][L - 2], 0, 0, 0);
+                }
+              }
+            }
+          }
+        }
+      }
+      // exact FP32 level sums -> FP64 with weights 2^{-b L}
+#pragma unroll
+      for (int tt = 0; tt < MAXT; ++tt) {
+#pragma unroll
+        for (int L = 2; L <= kSlices + 1; ++L) {
+          const double wgt = ldexp(1.0, -kSliceBits * L);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc_r[tt][i] += (double)lr[tt][L - 2][i] * wgt;
+            if (CPLX) acc_i[tt][i] += (double)li[tt][L - 2][i] * wgt;
+          }
+        }
+      }
+    }
+    // undo the row scales of the output rows
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+      const int tile = wave + tt * NW;
+      if (tile < ntiles) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double f = ldexp(1.0, (int)rexp[tile * 16 + f32_row(i, lq)]);
+          acc_r[tt][i] *= f;
+          acc_i[tt][i] *= f;
+        }
+      }
+    }
+  }
+  __syncthreads();  // X consumed by every wave; pb complete
+
+  double cm = 0.0;
+#pragma unroll
+  for (int tt = 0; tt < MAXT; ++tt) {
+    const int tile = wave + tt * NW;
+    if (tile < ntiles) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double p = pb[tile * 16 + f32_row(i, lq)];
+        acc_r[tt][i] *= p;
+        cm = fmax(cm, fabs(acc_r[tt][i]));
+        if (CPLX) {
+          acc_i[tt][i] *= p;
+          cm = fmax(cm, fabs(acc_i[tt][i]));
+        }
+      }
+    }
+  }
+  cm = fmax(cm, __shfl_xor(cm, 16));
+  cm = fmax(cm, __shfl_xor(cm, 32));
+  if (lane < 16) cmax[wave * kPanel + lane] = cm;
+  __syncthreads();
+  double M = 0.0;
+#pragma unroll
+  for (int w2 = 0; w2 < NW; ++w2) M = fmax(M, cmax[w2 * kPanel + ln]);
+  int e = 0;
+  if (M > 0.0) frexp(M, &e);
+  const double sc = ldexp(1.0, -e);
+  if (tid < kPanel) colexp[tid] += e;
+#pragma unroll
+  for (int tt = 0; tt < MAXT; ++tt) {
+    const int tile = wave + tt * NW;
+    if (tile < ntiles) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = tile * 16 + f32_row(i, lq);
+        Xr[m * kPanel + ln] = acc_r[tt][i] * sc;
+        if (CPLX) Xi[m * kPanel + ln] = acc_i[tt][i] * sc;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <bool CPLX, int NW, int MAXT, bool SPLIT>
 __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
   extern __shared__ double lds[];
   constexpr int NT = NW * 64;
   const int XR = I.xrows;
+  const int NS = I.n_sec;
   double* Xr = lds;                                    // [XR][16]
   double* Xi = lds + XR * kPanel;                      // [XR][16], complex only
   double* pa = lds + (CPLX ? 2 : 1) * XR * kPanel;     // propagator at the start position
   double* pb = pa + XR;                                // propagator in front of the next operator
   double* cmax = pb + XR;                              // [NW][16]
   double* red = cmax + NW * kPanel;                    // [NT] (x2 complex)
-  int* colexp = (int*)(red + (CPLX ? 2 : 1) * NT);     // [16] per-column power of two
+  double* s_dt = red + (CPLX ? 2 : 1) * NT;            // [kMaxOps] gap in front of every position
+  int* colexp = (int*)(s_dt + kMaxOps);                // [16] per-column power of two
+  int* s_dim = colexp + kPanel;                        // [NS] sector dimensions
+  int* s_eoff = s_dim + NS;                            // [NS] energy offsets
+  short* s_op = (short*)(s_eoff + NS);                 // [kMaxOps] operator codes, rotated order
+  short* s_path = s_op + kMaxOps;                      // [kMaxOps + 1] sector before every step
+  short* s_next = s_path + kMaxOps + 2;                // [NS * nops] sector map, when it fits
   __shared__ long long s_w;
 
   const int tid = threadIdx.x;
@@ -231,6 +551,15 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
   const int ln = lane & 15;  // column of the 16x16 tile held by this lane
   const int lq = lane >> 4;  // row group: D item i of this lane is row 4*i + lq
   const long long total = B.cfg_off[B.n_cfg];
+  const bool next_in_lds = I.next_lds != 0;
+
+  // per-impurity tables staged once for the lifetime of the workgroup
+  for (int i = tid; i < NS; i += NT) {
+    s_dim[i] = I.dim[i];
+    s_eoff[i] = I.eoff[i];
+  }
+  if (next_in_lds)
+    for (int i = tid; i < NS * I.nops; i += NT) s_next[i] = (short)I.next[i];
 
   for (;;) {
     if (tid == 0) s_w = (long long)atomicAdd(B.counter, 1u);
@@ -246,9 +575,9 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
     }
     const int c = lo;
     const int local = (int)(w - B.cfg_off[c]);
-    const StrRec* recs = B.rec + (long long)c * I.n_sec;
+    const StrRec* recs = B.rec + (long long)c * NS;
     lo = 0;
-    hi = I.n_sec - 1;
+    hi = NS - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (recs[mid].loc_off <= local) lo = mid; else hi = mid - 1;
@@ -256,17 +585,40 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
     const StrRec R = recs[lo];
     const int col0 = (local - R.loc_off) * kPanel;
     const int ncols = min(kPanel, R.width - col0);
+    const int G = (ncols + 3) >> 2;     // groups of 4 columns
+    const bool narrow = G <= 3;
     const long long base = B.offsets[c];
     const int n = (int)(B.offsets[c + 1] - base);
-    const double* tau = B.tau + base;
-    const int* ops = B.op + base;
 
-    int s = R.q_start, pos = R.jstar;
+    // the string in LDS: operator codes and gaps in rotated order, then the
+    // sectors it visits (one thread walks the sector map)
+    for (int t = tid; t < n; t += NT) {
+      const int p = (R.jstar + t) % n;
+      s_op[t] = (short)B.op[base + p];
+      s_dt[t] = p ? B.tau[base + p] - B.tau[base + p - 1] : B.tau[base] + I.beta - B.tau[base + n - 1];
+    }
     if (tid < kPanel) colexp[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+      int q = R.q_start;
+      s_path[0] = (short)q;
+      if (next_in_lds) {
+        for (int t = 0; t < n; ++t) {
+          q = s_next[q * I.nops + s_op[t]];
+          s_path[t + 1] = (short)q;
+        }
+      } else {
+        for (int t = 0; t < n; ++t) {
+          q = I.next[q * I.nops + s_op[t]];
+          s_path[t + 1] = (short)q;
+        }
+      }
+    }
     {
-      const int d = I.dim[s];
-      const double dt = (n == 0) ? I.beta : dtp(tau, n, pos, I.beta);
-      const double* e = I.esh + I.eoff[s];
+      const int s0 = R.q_start;
+      const int d = s_dim[s0];
+      const double dt = (n == 0) ? I.beta : s_dt[0];
+      const double* e = I.esh + s_eoff[s0];
       for (int r = tid; r < XR; r += NT) pa[r] = (r < d) ? exp(-dt * e[r]) : 0.0;
     }
     __syncthreads();
@@ -280,19 +632,33 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
         out.re = sum;
       }
     } else {
+      long long boff_next = I.boff[s_path[0] * I.nops + s_op[0]];
+      long long roff_next = SPLIT ? I.roff[s_path[0] * I.nops + s_op[0]] : 0;
       for (int t = 0; t < n - 1; ++t) {
-        const int idx = s * I.nops + ops[pos];
-        const int s2 = I.next[idx];
-        const int d_in = I.dim[s], d_out = I.dim[s2];
+        const long long roff_cur = roff_next;
+        const int s = s_path[t], s2 = s_path[t + 1];
+        const int d_in = s_dim[s], d_out = s_dim[s2];
         const int ld = (d_out + 15) & ~15;
         const int ntiles = ld >> 4;
-        const double* Fr = I.pool + I.boff[idx];
+        const double* Fr = I.pool + boff_next;
         const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
-        const int pos2 = (pos + 1 == n) ? 0 : pos + 1;
+        // block of the next step: its address is known from the path, load it now
+        boff_next = I.boff[s2 * I.nops + s_op[t + 1]];
+        if (SPLIT) roff_next = I.roff[s2 * I.nops + s_op[t + 1]];
         {
-          const double dt2 = dtp(tau, n, pos2, I.beta);
-          const double* e = I.esh + I.eoff[s2];
+          const double dt2 = s_dt[t + 1];
+          const double* e = I.esh + s_eoff[s2];
           for (int r = tid; r < ld; r += NT) pb[r] = (r < d_out) ? exp(-dt2 * e[r]) : 0.0;
+        }
+        if (SPLIT) {
+          step_split<CPLX, NW, MAXT>(t, Fr, Fi, I.rexp + roff_cur, ld, ntiles, d_in, pa, pb, Xr, Xi, cmax, colexp,
+                                     col0, ncols, lane, wave, tid);
+          continue;
+        }
+        if (narrow) {
+          step_narrow<CPLX, NW, MAXT>(t, Fr, Fi, ld, ntiles, d_in, pa, pb, Xr, Xi, cmax, colexp, col0, ncols,
+                                      G, lane, wave, tid);
+          continue;
         }
         dbl4 acc_r[MAXT], acc_i[MAXT];
 #pragma unroll
@@ -319,6 +685,7 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
           }
         } else {
           const int ksteps = (d_in + 3) >> 2;
+#pragma unroll 2
           for (int kc = 0; kc < ksteps; ++kc) {
             const int krow = kc * 4 + lq;
             const double br = Xr[krow * kPanel + ln];
@@ -384,17 +751,14 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
           }
         }
         __syncthreads();
-        s = s2;
-        pos = pos2;
       }
 
       // last operator: only the diagonal of F * X (rows col0 .. col0+ncols)
       {
-        const int idx = s * I.nops + ops[pos];
-        const int s2 = I.next[idx];
-        const int d_in = I.dim[s];
-        const int ld = (I.dim[s2] + 15) & ~15;
-        const double* Fr = I.pool + I.boff[idx];
+        const int s = s_path[n - 1];
+        const int d_in = s_dim[s];
+        const int ld = (s_dim[s_path[n]] + 15) & ~15;
+        const double* Fr = I.pool + boff_next;
         const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
         const int cc = tid & 15;
         double sr = 0.0, si = 0.0;
@@ -444,6 +808,288 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
     }
     if (tid == 0) B.res[w] = out;
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// chain, one wavefront per panel (sectors of at most 128 states)
+// ---------------------------------------------------------------------------
+// Every wavefront of the workgroup pulls its own work item (a panel of at most
+// kWavePanel columns) and runs the whole chain alone: all row tiles of the
+// block product are in its registers, so the per-column max is a wavefront
+// reduction and the step loop has no workgroup barrier.  Block products use
+// FP64 MFMA 4x4x4 on groups of four columns: lane l holds A[row l%16][k l/16],
+// B[k l/16][col l%4] and D[row 4*((l%16)/4) + l/16][col l%4].
+constexpr int kWavePanel = 8;
+constexpr int kWaveTiles = 8;  // 16-row tiles per wavefront: sectors up to 128 states
+
+template <bool CPLX>
+__host__ __device__ constexpr size_t wave_region_bytes(int xr) {
+  return (8 * ((size_t)(CPLX ? 2 : 1) * xr * kWavePanel + xr) + kMaxOps + 2 * ((size_t)kMaxOps + 2) + 15) & ~(size_t)15;
+}
+
+template <bool CPLX>
+__host__ __device__ constexpr size_t wave_lds_bytes(int xr, int n_sec, int next_entries) {
+  // per wavefront: X (kWavePanel columns, x2 complex), propagator, operator codes, path
+  return 4 * wave_region_bytes<CPLX>(xr) + 4 * 2 * (size_t)n_sec + 2 * (size_t)next_entries + 64;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, BatchArgs B) {
+  extern __shared__ double lds[];
+  const int XR = I.xrows;
+  const int NS = I.n_sec;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int ln = lane & 15, lq = lane >> 4, l3 = lane & 3;
+  const int orow = 4 * (ln >> 2) + lq;  // D row of this lane inside a 16-row tile
+
+  // per-wavefront region
+  const size_t per_wave = wave_region_bytes<CPLX>(XR);
+  char* my = (char*)lds + wave * per_wave;
+  double* Xr = (double*)my;
+  double* Xi = Xr + XR * kWavePanel;
+  double* pb = Xr + (CPLX ? 2 : 1) * XR * kWavePanel;
+  unsigned char* s_op = (unsigned char*)(pb + XR);
+  short* s_path = (short*)(s_op + kMaxOps);
+  // workgroup tables
+  int* s_dim = (int*)((char*)lds + 4 * per_wave);
+  int* s_eoff = s_dim + NS;
+  short* s_next = (short*)(s_eoff + NS);
+  const bool next_in_lds = I.next_lds != 0;
+  for (int i = tid; i < NS; i += 256) {
+    s_dim[i] = I.dim[i];
+    s_eoff[i] = I.eoff[i];
+  }
+  if (next_in_lds)
+    for (int i = tid; i < NS * I.nops; i += 256) s_next[i] = (short)I.next[i];
+  __syncthreads();
+
+  const long long total = B.cfg_off[B.n_cfg];
+  for (;;) {
+    long long w = 0;
+    if (lane == 0) w = (long long)atomicAdd(B.counter, 1u);
+    w = __shfl(w, 0);
+    if (w >= total) break;
+
+    int lo = 0, hi = B.n_cfg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (B.cfg_off[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int c = lo;
+    const int local = (int)(w - B.cfg_off[c]);
+    const StrRec* recs = B.rec + (long long)c * NS;
+    lo = 0;
+    hi = NS - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (recs[mid].loc_off <= local) lo = mid; else hi = mid - 1;
+    }
+    const StrRec R = recs[lo];
+    const int col0 = (local - R.loc_off) * kWavePanel;
+    const int ncols = min(kWavePanel, R.width - col0);
+    const int G = (ncols + 3) >> 2;
+    const long long base = B.offsets[c];
+    const int n = (int)(B.offsets[c + 1] - base);
+    const double* tau = B.tau + base;
+    const int* opg = B.op + base;
+
+    PanelRes out;
+    out.re = out.im = out.e2 = 0.0;
+    const int s0 = R.q_start;
+    if (n == 0) {
+      // partition-function string: trace of the diagonal propagator
+      const double* e = I.esh + s_eoff[s0];
+      double v = (lane < ncols) ? exp(-I.beta * e[col0 + lane]) : 0.0;
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      out.re = v;
+    } else {
+      // string in LDS: rotated operator codes, then the visited sectors
+      for (int t = lane; t < n; t += 64) s_op[t] = (unsigned char)opg[(R.jstar + t) % n];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) {
+        int q = s0;
+        s_path[0] = (short)q;
+        for (int t = 0; t < n; ++t) {
+          q = next_in_lds ? s_next[q * I.nops + s_op[t]] : I.next[q * I.nops + s_op[t]];
+          s_path[t + 1] = (short)q;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+
+      int ce[2] = {0, 0};  // power of two of columns g*4 + l3
+      long long boff_next = I.boff[s0 * I.nops + s_op[0]];
+      for (int t = 0; t < n - 1; ++t) {
+        const int s = s_path[t], s2 = s_path[t + 1];
+        const int d_in = s_dim[s], d_out = s_dim[s2];
+        const int ld = (d_out + 15) & ~15;
+        const int ntiles = ld >> 4;
+        const double* Fr = I.pool + boff_next;
+        const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
+        boff_next = I.boff[s2 * I.nops + s_op[t + 1]];
+        const int p1 = (R.jstar + t + 1) % n;  // position in front of the next operator
+        const double dt2 = p1 ? tau[p1] - tau[p1 - 1] : tau[0] + I.beta - tau[n - 1];
+        {
+          const double* e = I.esh + s_eoff[s2];
+          for (int r = lane; r < ld; r += 64) pb[r] = (r < d_out) ? exp(-dt2 * e[r]) : 0.0;
+        }
+        double acc_r[kWaveTiles][2], acc_i[kWaveTiles][2];
+#pragma unroll
+        for (int tt = 0; tt < kWaveTiles; ++tt) acc_r[tt][0] = acc_r[tt][1] = acc_i[tt][0] = acc_i[tt][1] = 0.0;
+        if (t == 0) {
+          const int p0 = R.jstar;
+          const double dt0 = p0 ? tau[p0] - tau[p0 - 1] : tau[0] + I.beta - tau[n - 1];
+          const double* e0 = I.esh + s_eoff[s];
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            const int cc = g * 4 + l3;
+            if (cc < ncols) {
+              const int k = col0 + cc;
+              const double p = exp(-dt0 * e0[k]);
+#pragma unroll
+              for (int tt = 0; tt < kWaveTiles; ++tt) {
+                if (tt < ntiles) {
+                  const long long a = (long long)k * ld + tt * 16 + orow;
+                  acc_r[tt][g] = Fr[a] * p;
+                  if (CPLX) acc_i[tt][g] = Fi[a] * p;
+                }
+              }
+            }
+          }
+        } else {
+          const int ksteps = (d_in + 3) >> 2;
+          for (int kc = 0; kc < ksteps; ++kc) {
+            const int krow = kc * 4 + lq;
+            double ar[kWaveTiles], ai[kWaveTiles];
+#pragma unroll
+            for (int tt = 0; tt < kWaveTiles; ++tt) {
+              if (tt < ntiles) {
+                const long long a = (long long)krow * ld + tt * 16 + ln;
+                ar[tt] = Fr[a];
+                ai[tt] = CPLX ? Fi[a] : 0.0;
+              }
+            }
+            const double b0r = Xr[krow * kWavePanel + l3];
+            const double b1r = Xr[krow * kWavePanel + 4 + l3];
+            const double b0i = CPLX ? Xi[krow * kWavePanel + l3] : 0.0;
+            const double b1i = CPLX ? Xi[krow * kWavePanel + 4 + l3] : 0.0;
+#pragma unroll
+            for (int tt = 0; tt < kWaveTiles; ++tt) {
+              if (tt < ntiles) {
+                acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b0r, acc_r[tt][0], 0, 0, 0);
+                if (CPLX) {
+                  acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[tt], b0i, acc_r[tt][0], 0, 0, 0);
+                  acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b0i, acc_i[tt][0], 0, 0, 0);
+                  acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[tt], b0r, acc_i[tt][0], 0, 0, 0);
+                }
+                if (G > 1) {
+                  acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b1r, acc_r[tt][1], 0, 0, 0);
+                  if (CPLX) {
+                    acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[tt], b1i, acc_r[tt][1], 0, 0, 0);
+                    acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b1i, acc_i[tt][1], 0, 0, 0);
+                    acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[tt], b1r, acc_i[tt][1], 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // propagator in front of the next operator, per-column max, rescale
+        double cm0 = 0.0, cm1 = 0.0;
+#pragma unroll
+        for (int tt = 0; tt < kWaveTiles; ++tt) {
+          if (tt < ntiles) {
+            const double p = pb[tt * 16 + orow];
+            acc_r[tt][0] *= p;
+            acc_r[tt][1] *= p;
+            cm0 = fmax(cm0, fabs(acc_r[tt][0]));
+            cm1 = fmax(cm1, fabs(acc_r[tt][1]));
+            if (CPLX) {
+              acc_i[tt][0] *= p;
+              acc_i[tt][1] *= p;
+              cm0 = fmax(cm0, fabs(acc_i[tt][0]));
+              cm1 = fmax(cm1, fabs(acc_i[tt][1]));
+            }
+          }
+        }
+        for (int off = 4; off < 64; off <<= 1) {
+          cm0 = fmax(cm0, __shfl_xor(cm0, off));
+          cm1 = fmax(cm1, __shfl_xor(cm1, off));
+        }
+        int e0 = 0, e1 = 0;
+        if (cm0 > 0.0) frexp(cm0, &e0);
+        if (cm1 > 0.0) frexp(cm1, &e1);
+        ce[0] += e0;
+        ce[1] += e1;
+        const double sc0 = ldexp(1.0, -e0), sc1 = ldexp(1.0, -e1);
+#pragma unroll
+        for (int tt = 0; tt < kWaveTiles; ++tt) {
+          if (tt < ntiles) {
+            const int m = tt * 16 + orow;
+            Xr[m * kWavePanel + l3] = acc_r[tt][0] * sc0;
+            Xr[m * kWavePanel + 4 + l3] = acc_r[tt][1] * sc1;
+            if (CPLX) {
+              Xi[m * kWavePanel + l3] = acc_i[tt][0] * sc0;
+              Xi[m * kWavePanel + 4 + l3] = acc_i[tt][1] * sc1;
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+
+      // last operator: diagonal of F * X; lane = column (l & 7) x k-partial (l >> 3)
+      {
+        const int s = s_path[n - 1];
+        const int d_in = s_dim[s];
+        const int ld = (s_dim[s_path[n]] + 15) & ~15;
+        const double* Fr = I.pool + boff_next;
+        const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
+        const int cc = lane & 7;
+        double sr = 0.0, si = 0.0;
+        if (cc < ncols) {
+          for (int k = lane >> 3; k < d_in; k += 8) {
+            const long long a = (long long)k * ld + col0 + cc;
+            const double fr = Fr[a], xr = Xr[k * kWavePanel + cc];
+            if (CPLX) {
+              const double fi = Fi[a], xi = Xi[k * kWavePanel + cc];
+              sr += fr * xr - fi * xi;
+              si += fr * xi + fi * xr;
+            } else {
+              sr += fr * xr;
+            }
+          }
+        }
+        for (int off = 8; off < 64; off <<= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        // exponent of column cc lives in lanes with l3 == cc % 4 (entry cc / 4)
+        const int ea = __shfl(ce[0], cc & 3), eb = __shfl(ce[1], cc & 3);
+        const int ec = (cc < 4) ? ea : eb;
+        const bool live = cc < ncols && (sr != 0.0 || si != 0.0);
+        int emax = live ? ec : INT_MIN;
+        for (int off = 1; off < 8; off <<= 1) emax = max(emax, __shfl_xor(emax, off));
+        if (emax != INT_MIN) {
+          const double f = live ? ldexp(1.0, ec - emax) : 0.0;
+          double vr = sr * f, vi = si * f;
+          for (int off = 1; off < 8; off <<= 1) {
+            vr += __shfl_xor(vr, off);
+            vi += __shfl_xor(vi, off);
+          }
+          out.re = vr;
+          out.im = vi;
+          out.e2 = (double)emax;
+        }
+      }
+    }
+    if (lane == 0) B.res[w] = out;
   }
 }
 
@@ -522,23 +1168,25 @@ struct Variant {
 };
 
 template <bool CPLX, int NW, int MAXT>
-Variant make_variant() {
-  return Variant{reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT>), NW, MAXT, CPLX};
+Variant make_variant(bool split) {
+  return Variant{split ? reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, true>)
+                       : reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, false>),
+                 NW, MAXT, CPLX};
 }
 
-bool pick_variant(const DevImp& imp, Variant* v) {
+bool pick_variant(const DevImp& imp, bool split, Variant* v) {
   const int tiles = imp.xrows / 16;
   if (imp.is_complex) {
-    if (tiles <= 8) *v = make_variant<true, 4, 2>();
-    else if (tiles <= 16) *v = make_variant<true, 8, 2>();
-    else if (tiles <= 32) *v = make_variant<true, 8, 4>();
-    else if (tiles <= 64) *v = make_variant<true, 16, 4>();
+    if (tiles <= 8) *v = make_variant<true, 4, 2>(split);
+    else if (tiles <= 16) *v = make_variant<true, 8, 2>(split);
+    else if (tiles <= 32) *v = make_variant<true, 8, 4>(split);
+    else if (tiles <= 64) *v = make_variant<true, 16, 4>(split);
     else return false;
   } else {
-    if (tiles <= 8) *v = make_variant<false, 4, 2>();
-    else if (tiles <= 16) *v = make_variant<false, 8, 2>();
-    else if (tiles <= 32) *v = make_variant<false, 8, 4>();
-    else if (tiles <= 64) *v = make_variant<false, 16, 4>();
+    if (tiles <= 8) *v = make_variant<false, 4, 2>(split);
+    else if (tiles <= 16) *v = make_variant<false, 8, 2>(split);
+    else if (tiles <= 32) *v = make_variant<false, 8, 4>(split);
+    else if (tiles <= 64) *v = make_variant<false, 16, 4>(split);
     else return false;
   }
   return true;
@@ -550,21 +1198,22 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 size_t chain_lds_bytes(const DevImp& imp) {
   Variant v;
-  if (!pick_variant(imp, &v)) return 0;
-  const size_t doubles = v.cplx ? (v.nw == 4 ? chain_lds_doubles<true, 4>(imp.xrows)
-                                  : v.nw == 8 ? chain_lds_doubles<true, 8>(imp.xrows)
-                                              : chain_lds_doubles<true, 16>(imp.xrows))
-                                : (v.nw == 4 ? chain_lds_doubles<false, 4>(imp.xrows)
-                                  : v.nw == 8 ? chain_lds_doubles<false, 8>(imp.xrows)
-                                              : chain_lds_doubles<false, 16>(imp.xrows));
-  return doubles * sizeof(double);
+  if (!pick_variant(imp, false, &v)) return 0;
+  const int ne = imp.next_lds ? imp.n_sec * imp.nops : 0;
+  const int xr = imp.xrows, ns = imp.n_sec;
+  return v.cplx ? (v.nw == 4 ? chain_lds_bytes_t<true, 4>(xr, ns, ne)
+                  : v.nw == 8 ? chain_lds_bytes_t<true, 8>(xr, ns, ne)
+                              : chain_lds_bytes_t<true, 16>(xr, ns, ne))
+                : (v.nw == 4 ? chain_lds_bytes_t<false, 4>(xr, ns, ne)
+                  : v.nw == 8 ? chain_lds_bytes_t<false, 8>(xr, ns, ne)
+                              : chain_lds_bytes_t<false, 16>(xr, ns, ne));
 }
 
 int chain_max_rows(int is_complex) { return is_complex ? 576 : 1024; }
 
-int chain_grid(const DevImp& imp, int device, size_t* lds_bytes) {
+int chain_grid(const DevImp& imp, int device, bool split, size_t* lds_bytes) {
   Variant v;
-  if (!pick_variant(imp, &v)) return 0;
+  if (!pick_variant(imp, split, &v)) return 0;
   const size_t bytes = chain_lds_bytes(imp);
   if (lds_bytes) *lds_bytes = bytes;
   if (bytes > kMaxLds) return 0;
@@ -577,9 +1226,37 @@ int chain_grid(const DevImp& imp, int device, size_t* lds_bytes) {
   return per_cu * cus;
 }
 
-hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream) {
+int wave_grid(const DevImp& imp, int device, size_t* lds_bytes) {
+  if (imp.xrows > kWaveTiles * 16) return 0;
+  const int ne = imp.next_lds ? imp.n_sec * imp.nops : 0;
+  const size_t bytes = imp.is_complex ? wave_lds_bytes<true>(imp.xrows, imp.n_sec, ne)
+                                      : wave_lds_bytes<false>(imp.xrows, imp.n_sec, ne);
+  if (lds_bytes) *lds_bytes = bytes;
+  if (bytes > kMaxLds) return 0;
+  const void* fn = imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true>)
+                                  : reinterpret_cast<const void*>(&k_chain_wave<false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, bytes) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu > 0 ? per_cu * cus : 0;
+}
+
+hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream) {
+  size_t bytes = 0;
+  const int ne = imp.next_lds ? imp.n_sec * imp.nops : 0;
+  bytes = imp.is_complex ? wave_lds_bytes<true>(imp.xrows, imp.n_sec, ne)
+                         : wave_lds_bytes<false>(imp.xrows, imp.n_sec, ne);
+  const void* fn = imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true>)
+                                  : reinterpret_cast<const void*>(&k_chain_wave<false>);
+  void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(256), args, bytes, stream);
+}
+
+hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream) {
   Variant v;
-  if (!pick_variant(imp, &v) || grid <= 0) return hipErrorInvalidValue;
+  if (!pick_variant(imp, split, &v) || grid <= 0) return hipErrorInvalidValue;
   const size_t bytes = chain_lds_bytes(imp);
   void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b)};
   return hipLaunchKernel(v.fn, dim3(grid), dim3(v.nw * 64), args, bytes, stream);

@@ -355,3 +355,44 @@ def test_blocks_beyond_lds_limit_are_reported(lib, ctx):
     with pytest.raises(lib.CtraceError) as e:
         lib.TraceContext(tab, arena_bytes=1 << 30)
     assert e.value.status == -7
+
+
+# ---------------------------------------------------------------------------
+# FP32-split precision (FP32 MFMA on exact integer slices, FP64 elsewhere)
+# ---------------------------------------------------------------------------
+
+def test_fp32_split_d_shell_vs_golden_and_fp64(lib, ctx):
+    tab, c = ctx("dshell")
+    g = load_golden("dshell_config1")
+    cfgs = make_configs(1, len(g["records"]))
+    say("[gpu] ctr_trace_batch FP32_SPLIT config1 x256")
+    out = c.trace_batch(cfgs, precision=lib.CTR_FP32_SPLIT)
+    check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                  "config1 fp32-split vs oracle")
+    f64 = c.trace_batch(cfgs)
+    worst = max(rel_err(pair(a), pair(b)) for a, b in zip(out, f64) if b["re"] != 0)
+    say(f"config1 fp32-split vs fp64 worst rel {worst:.2e}")
+
+
+@pytest.mark.parametrize("name", ["pshell_random", "dshell_so_random"])
+def test_fp32_split_complex_vs_golden(lib, ctx, name):
+    g = load_golden(name)
+    tab, c = ctx(g["impurity"])
+    strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
+    say(f"[gpu] ctr_trace_batch FP32_SPLIT {name}")
+    out = c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT)
+    check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                  name + " fp32-split")
+
+
+def test_fp32_split_rejects_unsupported_slices(lib, ctx):
+    tab, c = ctx("kanamori2")
+    o = lib.ctr_opts()
+    o.precision = lib.CTR_FP32_SPLIT
+    o.slices = 3
+    v = lib.ctr_value()
+    tau = np.array([1.0, 2.0])
+    op = np.array([1, 0], dtype=np.int32)
+    st = lib._lib.ctr_trace(c.ctx, 2, lib._ptr(tau, lib.ctypes.c_double), lib._ptr(op, lib.ctypes.c_int32),
+                            lib.ctypes.byref(o), lib.ctypes.byref(v))
+    assert st == -7
