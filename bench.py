@@ -29,6 +29,7 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     1: dict(name="dshell-kanamori-10^4-orders20-80", impurity="dshell", config_id=1),
     2: dict(name="fshell-slater-soc-10^4-orders40-160", impurity="fshell", config_id=2),
+    3: dict(name="fshell-slater-soc-cf-2000-orders60-200", impurity="fshell_cf", config_id=3),
 }
 
 
@@ -68,6 +69,67 @@ def algorithmic_flops(tab, strings):
     return total
 
 
+def chain_kernel_name(tab):
+    """Kernel the library's automatic choice runs for FP64 traces of this table:
+    the wavefront kernel for sectors of at most 128 states, the LDS workgroup
+    kernel while a 16-column panel fits LDS, the streaming kernel beyond."""
+    xr = (tab.max_dim + 15) // 16 * 16
+    if xr <= 128:
+        return "k_chain_wave"
+    if xr <= (576 if tab.is_complex else 1024):
+        return "k_chain"
+    return "k_chain_big"
+
+
+# HBM-side bytes per batch launch of the d-shell step (FETCH_SIZE + WRITE_SIZE,
+# scaled by the 1 GiB copy calibration), valid only for the kernel source they
+# were measured on; any change to the kernels makes the figure stale (None).
+TRAFFIC_MEASURED = {"k_chain_wave": {"source_sha256": None, "bytes": None}}
+
+
+def measured_traffic(kernel):
+    import hashlib
+
+    rec = TRAFFIC_MEASURED.get(kernel)
+    if not rec or not rec["source_sha256"]:
+        return None
+    src = os.path.join(ROOT, "paper_2010_08482_amd", "csrc", "ctrace_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return rec["bytes"] if sha == rec["source_sha256"] else None
+
+
+def lazy_leg(ctx, imp, strings, w_old):
+    """Metropolis decisions on pair-insertion proposals (App. D moves, lazy
+    trace of Sec. 3.3.1): each configuration is the old state, the proposal
+    inserts one pair, and the threshold is r |w_old| with r ~ U(0,1) drawn
+    first (every other acceptance factor taken as 1).  Times the lazy batch and
+    the full batch on the same proposals, both through the host entry points."""
+    from paper_2010_08482_amd import ctrace
+    from workloads.configs import insert_pair, pack
+
+    rng = np.random.Generator(np.random.PCG64(4242))
+    props = [insert_pair(rng, s, imp.n_flavors, imp.beta) for s in strings]
+    r = rng.uniform(0.0, 1.0, size=len(props))
+    la_old = np.array([ctrace.log_abs(v) for v in w_old[: len(props)]])
+    log_thr = np.where(np.isfinite(la_old), np.log(r) + la_old, -np.inf)
+    offs, tau, op = pack(props)
+    ctx.lazy_batch(offs, tau, op, log_thr)  # warm
+    t0 = time.perf_counter()
+    lz = ctx.lazy_batch(offs, tau, op, log_thr)
+    t_lazy = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    full = ctx.trace_packed(offs, tau, op)
+    t_full = time.perf_counter() - t0
+    la_new = np.array([ctrace.log_abs(v) for v in full])
+    rej = (lz["flags"] & ctrace.CTR_FLAG_REJECTED) != 0
+    should = la_new < log_thr
+    return {"proposals": len(props), "rejected_frac": float(rej.mean()),
+            "rejectable_frac": float(should.mean()),
+            "false_rejections": int(np.sum(rej & ~should)),
+            "decisions_per_s": len(props) / t_lazy, "full_traces_per_s": len(props) / t_full,
+            "speedup": t_full / t_lazy, "entry": "ctr_trace_lazy_batch vs ctr_trace_batch (host arrays)"}
+
+
 def cpu_baseline(imp, strings, seconds_budget=20.0):
     """The CPU oracle (dense full-space FP64 chain) on a bounded sample."""
     from threadpoolctl import threadpool_info
@@ -94,9 +156,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--n-configs", type=int, default=0, help="use only the first N configurations (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-sample", type=int, default=200)
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split leg")
+    ap.add_argument("--lazy-sample", type=int, default=-1,
+                    help="pair-insertion proposals for the lazy leg (-1 = every configuration, 0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once with a plain device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -115,7 +180,7 @@ def main():
     wl = WORKLOADS[args.workload]
     imp = make_impurity(wl["impurity"])
     tab = build_sectors(imp)
-    strings = make_configs(wl["config_id"])
+    strings = make_configs(wl["config_id"], args.n_configs or None)
     n_cfg = len(strings)
     print(f"[bench] workload {wl['name']}: {n_cfg} configurations, {tab.n_sectors} sectors, "
           f"largest block {tab.max_dim}", file=sys.stderr, flush=True)
@@ -199,6 +264,10 @@ def main():
     launches_per_step = launches / max(args.steps, 1)
     achieved = flops / launches_per_step / (per_launch_ms * 1e-3) / 1e12 if per_launch_ms > 0 else None
 
+    lazy = None
+    if args.lazy_sample != 0:
+        lazy = lazy_leg(ctx, imp, strings[: args.lazy_sample] if args.lazy_sample > 0 else strings, out)
+
     # single-configuration latency through the host-pointer entry point
     lat = []
     for s in strings[: args.latency_sample]:
@@ -240,18 +309,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "impurity": wl["impurity"], "n_configs": n_cfg,
+        "config": {"workload": wl["name"] if not args.n_configs else f"{wl['name']} (first {n_cfg})",
+                   "impurity": wl["impurity"], "n_configs": n_cfg,
                    "sectors": int(tab.n_sectors), "largest_block": int(tab.max_dim), "beta": tab.beta,
                    "complex": bool(tab.is_complex), "precision": "FP64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
-                     "kernel": "k_chain", "algorithmic_flop_per_launch": flops / launches_per_step,
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
+                     "traffic": measured_traffic(chain_kernel_name(tab)),
+                     "kernel": chain_kernel_name(tab), "algorithmic_flop_per_launch": flops / launches_per_step,
                      "launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "entry": "ctr_trace (one configuration, host pointers)"},
         "max_rel_err_vs_oracle_sample": rel,
         "fp32_split": split,
+        "lazy": lazy,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -24,7 +24,7 @@
  *    ctr_create.  Host-pointer entry points return after the result is on
  *    the host; *_device entry points only enqueue.
  *  - Memory: the library never allocates device memory.  Everything it
- *    keeps (operator blocks, tables, per-call scratch) is carved out of the
+ *    keeps (operator blocks, tables, kernel buffers, per-call scratch) is carved out of the
  *    arena the caller passes to ctr_create (pre-allocated device pool, as in
  *    Sec. 3.3.2).  Running out of arena returns CTR_ERR_OOM and leaves the
  *    context usable.
@@ -75,10 +75,21 @@ typedef struct {
   int32_t flags;       /* CTR_FLAG_* */
 } ctr_value;
 
+/* ctr_opts.kernel: which chain kernel runs the block products */
+enum {
+  CTR_KERNEL_AUTO = 0,    /* wavefront kernel for sectors <= 128 states (FP64), else the
+                             LDS-resident workgroup kernel when the panel fits LDS, else streaming */
+  CTR_KERNEL_WAVE = 1,    /* one wavefront per 8-column panel; sectors <= 128 states, FP64 only */
+  CTR_KERNEL_BLOCK = 2,   /* one workgroup per 16-column panel, X in LDS (<= 1024 real / 576 complex) */
+  CTR_KERNEL_STREAM = 3   /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
+};
+
 typedef struct {
   int32_t precision;   /* CTR_FP64 (default) or CTR_FP32_SPLIT */
-  int32_t slices;      /* CTR_FP32_SPLIT: slices per operand, 0 = library default */
-  int32_t reserved[2]; /* must be 0 */
+  int32_t slices;      /* CTR_FP32_SPLIT: slices per operand; 0 or 6 (6 slices of 8 bits) */
+  int32_t kernel;      /* CTR_KERNEL_*; a kernel that cannot run this impurity/precision
+                          gives CTR_ERR_UNSUPPORTED */
+  int32_t reserved;    /* must be 0 */
 } ctr_opts;
 
 /*
@@ -149,8 +160,8 @@ void ctr_destroy(ctr_ctx *ctx);
  * creator blocks materialised, complex split into planes).  Host buffers
  * are read during the call only.  Replaces any previous impurity and
  * resets the arena.  Errors: CTR_ERR_ARG (inconsistent tables, missing
- * block), CTR_ERR_OOM, CTR_ERR_UNSUPPORTED (largest sector beyond the
- * kernels' limit), CTR_ERR_DEVICE.
+ * block), CTR_ERR_OOM, CTR_ERR_UNSUPPORTED (more than 32767 sectors),
+ * CTR_ERR_DEVICE.
  */
 ctr_status ctr_set_impurity(ctr_ctx *ctx, const ctr_impurity *imp);
 

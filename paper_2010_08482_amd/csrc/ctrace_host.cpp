@@ -32,7 +32,9 @@ struct ctr_ctx {
   long long max_panels_per_cfg = 0;
   int grid = 0;
   int grid_split = 0;
-  int grid_wave = 0;  // > 0: FP64 traces use the wavefront-per-panel kernel (panels of 8 columns)
+  int grid_wave = 0;  // wavefront-per-panel kernel (panels of 8 columns), 0 = not applicable
+  int grid_big = 0;   // streaming kernel
+  double* xbuf = nullptr;  // the streaming kernel's per-workgroup X buffers
   unsigned int* counter = nullptr;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -89,7 +91,7 @@ ctr_status check_config(ctr_ctx* ctx, long long n, const double* tau, const int3
 
 size_t scratch_per_cfg(const ctr_ctx* ctx) {
   // panels counted with the narrowest panel width any kernel uses (upper bound)
-  return (size_t)ctx->n_sec * sizeof(StrRec) + 3 * sizeof(int) + 2 * sizeof(double) + sizeof(long long) +
+  return (size_t)ctx->n_sec * sizeof(StrRec) + 4 * sizeof(int) + 5 * sizeof(double) + sizeof(long long) +
          (size_t)ctx->max_panels_per_cfg * sizeof(PanelRes);
 }
 
@@ -103,13 +105,18 @@ bool carve(ctr_ctx* ctx, Bump& b, int n_cfg, BatchArgs& a) {
   a.cfg_logB = (double*)b.take((size_t)n_cfg * sizeof(double));
   a.cfg_off = (long long*)b.take((size_t)(n_cfg + 1) * sizeof(long long));
   a.res = (PanelRes*)b.take((size_t)n_cfg * ctx->max_panels_per_cfg * sizeof(PanelRes));
+  a.cfg_lthr = (double*)b.take((size_t)n_cfg * sizeof(double));
+  a.cfg_bsum = (unsigned long long*)b.take((size_t)n_cfg * sizeof(unsigned long long));
+  a.cfg_rej = (int*)b.take((size_t)n_cfg * sizeof(int));
   a.counter = ctx->counter;
-  return a.rec && a.cfg_cnt && a.cfg_flags && a.cfg_nstr && a.cfg_logB && a.cfg_off && a.res;
+  return a.rec && a.cfg_cnt && a.cfg_flags && a.cfg_nstr && a.cfg_logB && a.cfg_off && a.res && a.cfg_lthr &&
+         a.cfg_bsum && a.cfg_rej;
 }
 
-ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split) {
-  const bool wave = !split && ctx->grid_wave > 0;
-  a.panel = wave ? ctr::kWavePanelHost : ctr::kPanel;
+enum class Kernel { Wave, Block, Stream };
+
+ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kernel kind) {
+  a.panel = kind == Kernel::Wave ? ctr::kWavePanelHost : ctr::kPanel;
   hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
   if (plan_only) return CTR_OK;
@@ -121,8 +128,13 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split) {
     HIP_TRY(ctx, hipEventCreate(&t1));
     HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
   }
-  e = wave ? ctr::launch_chain_wave(ctx->imp, a, ctx->grid_wave, ctx->stream)
-           : ctr::launch_chain(ctx->imp, a, split, split ? ctx->grid_split : ctx->grid, ctx->stream);
+  switch (kind) {
+    case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, ctx->grid_wave, ctx->stream); break;
+    case Kernel::Block:
+      e = ctr::launch_chain(ctx->imp, a, split, split ? ctx->grid_split : ctx->grid, ctx->stream);
+      break;
+    case Kernel::Stream: e = ctr::launch_chain_big(ctx->imp, a, ctx->xbuf, ctx->grid_big, ctx->stream); break;
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "chain kernel");
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
@@ -141,26 +153,51 @@ ctr_status ready(ctr_ctx* ctx) {
   return CTR_OK;
 }
 
-ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split) {
+ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* kind) {
   *split = false;
-  if (!opts) return CTR_OK;
-  if (opts->reserved[0] || opts->reserved[1]) return fail(ctx, CTR_ERR_ARG, "ctr_opts.reserved must be 0");
-  if (opts->precision == CTR_FP64) return CTR_OK;
-  if (opts->precision == CTR_FP32_SPLIT) {
-    if (opts->slices != 0 && opts->slices != 6)
-      return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT supports 6 slices of 8 bits (slices = 0 or 6)");
-    if (ctx->grid_split <= 0) return fail(ctx, CTR_ERR_UNSUPPORTED, "split kernel does not fit the device");
-    *split = true;
-    return CTR_OK;
+  int want = CTR_KERNEL_AUTO;
+  if (opts) {
+    if (opts->reserved) return fail(ctx, CTR_ERR_ARG, "ctr_opts.reserved must be 0");
+    if (opts->precision == CTR_FP32_SPLIT) {
+      if (opts->slices != 0 && opts->slices != 6)
+        return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT supports 6 slices of 8 bits (slices = 0 or 6)");
+      *split = true;
+    } else if (opts->precision != CTR_FP64) {
+      return fail(ctx, CTR_ERR_ARG, "unknown precision");
+    }
+    want = opts->kernel;
+    if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_STREAM) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
   }
-  return fail(ctx, CTR_ERR_ARG, "unknown precision");
+  const bool wave_ok = !*split && ctx->grid_wave > 0;
+  const bool block_ok = (*split ? ctx->grid_split : ctx->grid) > 0;
+  const bool stream_ok = !*split && ctx->grid_big > 0;
+  switch (want) {
+    case CTR_KERNEL_AUTO:
+      if (wave_ok) *kind = Kernel::Wave;
+      else if (block_ok) *kind = Kernel::Block;
+      else if (stream_ok) *kind = Kernel::Stream;
+      else return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel can run this impurity in this precision");
+      return CTR_OK;
+    case CTR_KERNEL_WAVE:
+      if (!wave_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "wavefront kernel needs FP64 and sectors <= 128 states");
+      *kind = Kernel::Wave;
+      return CTR_OK;
+    case CTR_KERNEL_BLOCK:
+      if (!block_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "the panel of the largest sector does not fit LDS");
+      *kind = Kernel::Block;
+      return CTR_OK;
+    default:
+      if (!stream_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "streaming kernel runs FP64 only");
+      *kind = Kernel::Stream;
+      return CTR_OK;
+  }
 }
 
 // Host-pointer batch: validates, then runs arena-sized chunks; `mode` 0 =
 // traces, 1 = bounds only (out_bound), thresholds optional.
 ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
                       const double* log_thr, ctr_value* out, double* out_bound, int mode, bool split,
-                      BatchArgs* last = nullptr) {
+                      Kernel kind, BatchArgs* last = nullptr) {
   if (n_cfg < 0 || (n_cfg > 0 && (!offsets || (!out && !out_bound))))
     return fail(ctx, CTR_ERR_ARG, "null argument");
   if (n_cfg == 0) return CTR_OK;
@@ -210,7 +247,7 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     a.op = d_op;
     a.log_thr = d_thr;
     a.out = d_out;
-    ctr_status s = enqueue(ctx, a, mode == 1, split);
+    ctr_status s = enqueue(ctx, a, mode == 1, split, kind);
     if (s != CTR_OK) return s;
     if (mode == 1) {
       HIP_TRY(ctx, hipMemcpyAsync(out_bound + c0, a.cfg_logB, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -306,11 +343,6 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
         return fail(ctx, CTR_ERR_ARG, "next table: c+_f then c_f does not return to the sector");
     }
   if (ns > 32767) return fail(ctx, CTR_ERR_UNSUPPORTED, "more than 32767 sectors");
-  if (maxd > ctr::chain_max_rows(cplx))
-    return fail(ctx, CTR_ERR_UNSUPPORTED, "largest sector (" + std::to_string(maxd) +
-                                              ") exceeds the LDS-resident chain kernel limit of " +
-                                              std::to_string(ctr::chain_max_rows(cplx)));
-
   // energies: global minimum, per-sector minimum, shifted and padded copies
   std::vector<double> emin(ns), esh;
   std::vector<int> eoff(ns);
@@ -476,12 +508,17 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   long long mp = 0;
   for (int q = 0; q < ns; ++q) mp += (dim[q] + ctr::kWavePanelHost - 1) / ctr::kWavePanelHost;
   ctx->max_panels_per_cfg = mp;
-  size_t lds = 0;
-  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, false, &lds);
+  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, false, nullptr);
   ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, true, nullptr);
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
-  if (ctx->grid <= 0)
-    return fail(ctx, CTR_ERR_UNSUPPORTED, "chain kernel does not fit the device (LDS " + std::to_string(lds) + " B)");
+  ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
+  ctx->xbuf = nullptr;
+  if (ctx->grid_big > 0) {
+    ctx->xbuf = (double*)b.take(ctr::big_xbuf_doubles(ctx->imp, ctx->grid_big) * sizeof(double));
+    if (!ctx->xbuf) return fail(ctx, CTR_ERR_OOM, "arena too small for the streaming kernel's buffers");
+  }
+  if (ctx->grid <= 0 && ctx->grid_wave <= 0 && ctx->grid_big <= 0)
+    return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel fits this impurity on the device");
   ctx->resident = align_up(b.off);
   ctx->loaded = true;
   return CTR_OK;
@@ -492,8 +529,9 @@ ctr_status ctr_trace_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, 
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
   bool split = false;
-  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
-  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split);
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
+  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind);
 }
 
 ctr_status ctr_trace(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, const ctr_opts* opts,
@@ -509,9 +547,10 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offs
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
   bool split = false;
-  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
   if (n_cfg > 0 && !log_threshold) return fail(ctx, CTR_ERR_ARG, "null log_threshold");
-  return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split);
+  return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split, kind);
 }
 
 ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double* log_bound) {
@@ -519,7 +558,10 @@ ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32
   if (s != CTR_OK) return s;
   if (!log_bound || n_ops < 0) return fail(ctx, CTR_ERR_ARG, "bad argument");
   const int64_t offs[2] = {0, n_ops};
-  return host_batch(ctx, 1, offs, tau, op, nullptr, nullptr, log_bound, 1, false);
+  bool split = false;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, nullptr, &split, &kind)) != CTR_OK) return s;
+  return host_batch(ctx, 1, offs, tau, op, nullptr, nullptr, log_bound, 1, false, kind);
 }
 
 ctr_status ctr_strings(ctr_ctx* ctx, int32_t n_ops, const int32_t* op, int32_t* q0_out, int32_t* n_out) {
@@ -530,7 +572,10 @@ ctr_status ctr_strings(ctr_ctx* ctx, int32_t n_ops, const int32_t* op, int32_t* 
   const int64_t offs[2] = {0, n_ops};
   double lb = 0.0;
   BatchArgs a{};
-  if ((s = host_batch(ctx, 1, offs, tau.data(), op, nullptr, nullptr, &lb, 1, false, &a)) != CTR_OK) return s;
+  bool split = false;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, nullptr, &split, &kind)) != CTR_OK) return s;
+  if ((s = host_batch(ctx, 1, offs, tau.data(), op, nullptr, nullptr, &lb, 1, false, kind, &a)) != CTR_OK) return s;
   std::vector<StrRec> rec(ctx->n_sec);
   HIP_TRY(ctx, hipMemcpyAsync(rec.data(), a.rec, rec.size() * sizeof(StrRec), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -546,7 +591,8 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
   ctr_status s = ready(ctx);
   if (s != CTR_OK) return s;
   bool split = false;
-  if ((s = check_opts(ctx, opts, &split)) != CTR_OK) return s;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
   if (n_cfg < 0 || (n_cfg > 0 && (!d_offsets || !d_out))) return fail(ctx, CTR_ERR_ARG, "null argument");
   const size_t free_bytes = ctx->arena_bytes - ctx->resident;
   const size_t per_cfg = scratch_per_cfg(ctx) + 64;
@@ -562,7 +608,7 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
     a.op = d_op;
     a.log_thr = nullptr;
     a.out = d_out + c0;
-    if ((s = enqueue(ctx, a, false, split)) != CTR_OK) return s;
+    if ((s = enqueue(ctx, a, false, split, kind)) != CTR_OK) return s;
     c0 += m;
   }
   return CTR_OK;

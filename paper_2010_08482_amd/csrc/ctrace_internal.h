@@ -51,7 +51,17 @@ struct StrRec {
   int pad;
   double L;        // sum over positions of dt * (lowest energy of the sector - E0)
   double logB;     // log of the lazy bound of this string (without the -beta*E0 part)
+  unsigned long long u_full;  // lazy traces: initial bound of a full panel, in threshold units
+  unsigned long long u_last;  // same for the last (possibly narrower) panel
 };
+
+// Lazy traces keep the running bound sum of a configuration exactly, in
+// integer units of 2^-kLazyUnitBits times its threshold: a panel bound b
+// counts ceil(b / unit) (at most kLazyCap), and the configuration is
+// rejected once the sum is below 2^kLazyUnitBits.  Integer sums do not
+// cancel, whatever the ratio of the threshold to the initial bound.
+constexpr int kLazyUnitBits = 30;
+constexpr int kLazyCapBits = 40;
 
 struct PanelRes {
   double re, im;   // mantissa
@@ -74,6 +84,10 @@ struct BatchArgs {
   PanelRes* res;             // [total panels]
   unsigned int* counter;     // persistent-kernel work counter
   ctr_value* out;            // [n_cfg]
+  // lazy traces (log_thr != nullptr)
+  double* cfg_lthr;                  // [n_cfg] log threshold + beta*E0 (units of the string bounds)
+  unsigned long long* cfg_bsum;      // [n_cfg] running sum of panel bounds in threshold units
+  int* cfg_rej;                      // [n_cfg] 1 once the bound sum fell below the threshold
 };
 
 // Launchers (ctrace_kernels.hip).  All enqueue on `stream`.
@@ -89,5 +103,9 @@ int chain_max_rows(int is_complex);
 int wave_grid(const DevImp& imp, int device, size_t* lds_bytes);
 hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream);
 constexpr int kWavePanelHost = 8;
+// Streaming chain kernel (any sector size; X in per-workgroup global buffers).
+int big_grid(const DevImp& imp, int device, size_t* lds_bytes);
+size_t big_xbuf_doubles(const DevImp& imp, int grid);
+hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf, int grid, hipStream_t stream);
 
 }  // namespace ctr

@@ -18,6 +18,8 @@
 //              panel results of all strings in a fixed order.
 #include <math.h>
 
+#include <algorithm>
+
 #include "ctrace_internal.h"
 
 namespace ctr {
@@ -30,6 +32,17 @@ __device__ __forceinline__ double dtp(const double* tau, int n, int p, double be
   return p ? tau[p] - tau[p - 1] : tau[0] + beta - tau[n - 1];
 }
 
+// Lazy traces: a bound given by its log (without the -beta*E0 part), in
+// integer units of 2^-kLazyUnitBits times the threshold exp(lthr), rounded up
+// and capped at 2^kLazyCapBits (a capped panel alone exceeds the threshold,
+// so the configuration cannot be rejected while it stays capped).
+__device__ __forceinline__ unsigned long long lazy_units(double logb, double lthr) {
+  const double ln2 = 0.69314718055994530942;
+  const double x = logb - lthr + kLazyUnitBits * ln2;
+  if (!(x < kLazyCapBits * ln2)) return 1ull << kLazyCapBits;  // also a NaN
+  return (unsigned long long)ceil(exp(x) * (1.0 + 1e-12));
+}
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
@@ -40,6 +53,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
   __shared__ int s_bad;
   __shared__ int s_scan[kPlanThreads];
   __shared__ double s_red[kPlanThreads];
+  __shared__ unsigned long long s_units[kPlanThreads];
 
   const int c = blockIdx.x;
   const int t = threadIdx.x;
@@ -71,6 +85,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
   const int q_hi = min(q_lo + chunk, I.n_sec);
   StrRec* recs = B.rec + (long long)c * I.n_sec;
   int my_panels = 0, my_nstr = 0;
+  unsigned long long my_units = 0;
   double my_max = -INFINITY;
   for (int q0 = q_lo; q0 < q_hi; ++q0) {
     StrRec R;
@@ -82,6 +97,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
     R.pad = 0;
     R.L = 0.0;
     R.logB = -INFINITY;
+    R.u_full = R.u_last = 0;
     if (!bad) {
       int s = q0, best = I.dim[q0], jstar = 0, qbest = q0;
       double L = 0.0, logn = 0.0;
@@ -110,6 +126,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
         R.n_panels = (best + B.panel - 1) / B.panel;
         R.L = L;
         R.logB = log((double)best) - L + logn;
+        if (B.log_thr != nullptr) {
+          // initial panel bounds: ncols * exp(-L) * (block norms), ncols = panel width or the remainder
+          const double lthr = B.log_thr[c] + I.beta * I.E0;
+          const int last = best - (R.n_panels - 1) * B.panel;
+          R.u_full = lazy_units(log((double)B.panel) - L + logn, lthr);
+          R.u_last = lazy_units(log((double)last) - L + logn, lthr);
+          my_units += (unsigned long long)(R.n_panels - 1) * R.u_full + R.u_last;
+        }
         my_panels += R.n_panels;
         my_nstr += 1;
         my_max = fmax(my_max, R.logB);
@@ -150,11 +174,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
       if (recs[q0].n_panels > 0) my_sum += exp(recs[q0].logB - gmax);
   s_red[t] = my_sum;
   s_scan[t] = my_nstr;
+  s_units[t] = my_units;
   __syncthreads();
   for (int off = kPlanThreads / 2; off > 0; off >>= 1) {
     if (t < off) {
       s_red[t] += s_red[t + off];
       s_scan[t] += s_scan[t + off];
+      s_units[t] += s_units[t + off];
     }
     __syncthreads();
   }
@@ -164,9 +190,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(DevImp I, BatchArgs B) {
     int flags = bad ? CTR_FLAG_INVALID : 0;
     int cnt = bad ? 0 : total;
     if (!bad && nstr == 0) flags |= CTR_FLAG_ZERO;
-    if (!bad && nstr > 0 && B.log_thr != nullptr && logB < B.log_thr[c]) {
-      flags |= CTR_FLAG_REJECTED;
-      cnt = 0;
+    B.cfg_rej[c] = 0;
+    if (B.log_thr != nullptr) {
+      B.cfg_lthr[c] = B.log_thr[c] + I.beta * I.E0;
+      B.cfg_bsum[c] = s_units[0];
+      if (!bad && nstr > 0 && logB < B.log_thr[c]) {
+        flags |= CTR_FLAG_REJECTED;
+        cnt = 0;
+      }
     }
     B.cfg_cnt[c] = cnt;
     B.cfg_flags[c] = flags;
@@ -212,6 +243,48 @@ __host__ __device__ constexpr size_t chain_lds_bytes_t(int xr, int n_sec, int ne
   return 8 * ((size_t)(CPLX ? 2 : 1) * xr * kPanel + 2 * (size_t)xr + NW * kPanel + (CPLX ? 2 : 1) * NW * 64 +
               kMaxOps) +
          4 * (kPanel + 2 * (size_t)n_sec) + 2 * (2 * (size_t)kMaxOps + 2 + next_entries);
+}
+
+// Lazy traces: every panel starts with its share of the string bound,
+// ncols * exp(-L) times the block norms, and replaces it while its chain runs
+// by sqrt(ncols) * ||X||_F * exp(-L) (the sum of ncols diagonal entries of
+// R * X is at most sqrt(ncols) ||R X||_F, and the remaining blocks and shifted
+// propagators R have norm <= 1), and at its end by the modulus of its exact
+// contribution.  The configuration's running sum (integer threshold units)
+// only decreases; once it is below the threshold the configuration is
+// rejected and its remaining panels stop.
+__device__ __forceinline__ bool lazy_rejected(const BatchArgs& B, int c) {
+  return __hip_atomic_load(B.cfg_rej + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ unsigned long long lazy_initial(const StrRec& R, int local) {
+  return (local - R.loc_off == R.n_panels - 1) ? R.u_last : R.u_full;
+}
+
+// Replaces the panel's bound *ucur by the bound with log logb if that is
+// smaller; returns true if the configuration is now rejected.
+__device__ __forceinline__ bool lazy_update(const BatchArgs& B, int c, unsigned long long* ucur, double logb) {
+  const unsigned long long unew = lazy_units(logb, B.cfg_lthr[c]);
+  if (unew >= *ucur) return false;
+  const unsigned long long delta = unew - *ucur;  // two's complement: subtracts
+  *ucur = unew;
+  const unsigned long long sum = atomicAdd(B.cfg_bsum + c, delta) + delta;
+  if (sum < (1ull << kLazyUnitBits)) {
+    atomicExch(B.cfg_rej + c, 1);
+    return true;
+  }
+  return false;
+}
+
+// log of sum_j exp(a_j) over the 4 lanes of a quad-aligned group (xor 1, 2)
+__device__ __forceinline__ double logsumexp_quad(double a) {
+  double m = a;
+  m = fmax(m, __shfl_xor(m, 1));
+  m = fmax(m, __shfl_xor(m, 2));
+  double e = (m == -INFINITY) ? 0.0 : exp(a - m);
+  e += __shfl_xor(e, 1);
+  e += __shfl_xor(e, 2);
+  return (m == -INFINITY) ? -INFINITY : m + log(e);
 }
 
 // One chain step for a panel of at most 12 columns: FP64 MFMA 4x4x4 with four
@@ -544,6 +617,7 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
   short* s_path = s_op + kMaxOps;                      // [kMaxOps + 1] sector before every step
   short* s_next = s_path + kMaxOps + 2;                // [NS * nops] sector map, when it fits
   __shared__ long long s_w;
+  __shared__ int s_rej;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -625,6 +699,9 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
 
     PanelRes out;
     out.re = out.im = out.e2 = 0.0;
+    const bool lazy = B.log_thr != nullptr;
+    unsigned long long ucur = lazy ? lazy_initial(R, local) : 0;  // used by thread 0
+    bool dead = false;
     if (n == 0) {
       if (tid == 0) {
         double sum = 0.0;
@@ -635,6 +712,14 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
       long long boff_next = I.boff[s_path[0] * I.nops + s_op[0]];
       long long roff_next = SPLIT ? I.roff[s_path[0] * I.nops + s_op[0]] : 0;
       for (int t = 0; t < n - 1; ++t) {
+        if (lazy) {
+          if (tid == 0) s_rej = lazy_rejected(B, c) ? 1 : 0;
+          __syncthreads();
+          if (s_rej) {
+            dead = true;
+            break;
+          }
+        }
         const long long roff_cur = roff_next;
         const int s = s_path[t], s2 = s_path[t + 1];
         const int d_in = s_dim[s], d_out = s_dim[s2];
@@ -754,7 +839,7 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
       }
 
       // last operator: only the diagonal of F * X (rows col0 .. col0+ncols)
-      {
+      if (!dead) {
         const int s = s_path[n - 1];
         const int d_in = s_dim[s];
         const int ld = (s_dim[s_path[n]] + 15) & ~15;
@@ -803,6 +888,10 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
             out.im = vi;
             out.e2 = (double)emax;
           }
+          if (lazy) {
+            const double a = hypot(out.re, out.im);
+            lazy_update(B, c, &ucur, a > 0.0 ? log(a) + out.e2 * 0.69314718055994530942 - R.L : -INFINITY);
+          }
         }
       }
     }
@@ -834,7 +923,7 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int xr, int n_sec, int next_
   return 4 * wave_region_bytes<CPLX>(xr) + 4 * 2 * (size_t)n_sec + 2 * (size_t)next_entries + 64;
 }
 
-template <bool CPLX>
+template <bool CPLX, bool LAZY>
 __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, BatchArgs B) {
   extern __shared__ double lds[];
   const int XR = I.xrows;
@@ -899,6 +988,9 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
     PanelRes out;
     out.re = out.im = out.e2 = 0.0;
     const int s0 = R.q_start;
+    constexpr bool lazy = LAZY;
+    unsigned long long ucur = lazy ? lazy_initial(R, local) : 0;
+    bool dead = false;
     if (n == 0) {
       // partition-function string: trace of the diagonal propagator
       const double* e = I.esh + s_eoff[s0];
@@ -924,6 +1016,13 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
       int ce[2] = {0, 0};  // power of two of columns g*4 + l3
       long long boff_next = I.boff[s0 * I.nops + s_op[0]];
       for (int t = 0; t < n - 1; ++t) {
+        if (lazy) {
+          int rj = (lane == 0) ? (int)lazy_rejected(B, c) : 0;
+          if (__shfl(rj, 0)) {
+            dead = true;
+            break;
+          }
+        }
         const int s = s_path[t], s2 = s_path[t + 1];
         const int d_in = s_dim[s], d_out = s_dim[s2];
         const int ld = (d_out + 15) & ~15;
@@ -1042,10 +1141,44 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        if (lazy && (t & 3) == 3) {
+          // Frobenius norm of the panel: columns l3 and 4 + l3 of every lane
+          double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+          for (int tt = 0; tt < kWaveTiles; ++tt) {
+            if (tt < ntiles) {
+              const double a0 = acc_r[tt][0] * sc0, a1 = acc_r[tt][1] * sc1;
+              q0 += a0 * a0;
+              q1 += a1 * a1;
+              if (CPLX) {
+                const double b0 = acc_i[tt][0] * sc0, b1 = acc_i[tt][1] * sc1;
+                q0 += b0 * b0;
+                q1 += b1 * b1;
+              }
+            }
+          }
+          for (int off = 4; off < 64; off <<= 1) {
+            q0 += __shfl_xor(q0, off);
+            q1 += __shfl_xor(q1, off);
+          }
+          const double A0 = q0 > 0.0 ? log(q0) + 2.0 * ce[0] * 0.69314718055994530942 : -INFINITY;
+          const double A1 = q1 > 0.0 ? log(q1) + 2.0 * ce[1] * 0.69314718055994530942 : -INFINITY;
+          const double mA = fmax(A0, A1);
+          const double lane_sum = (mA == -INFINITY) ? -INFINITY : mA + log(exp(A0 - mA) + exp(A1 - mA));
+          const double logF2 = logsumexp_quad(lane_sum);
+          int rj = 0;
+          if (lane == 0 && logF2 > -INFINITY)
+            rj = lazy_update(B, c, &ucur, 0.5 * (logF2 + log((double)ncols)) - R.L);
+          ucur = __shfl(ucur, 0);
+          if (__shfl(rj, 0)) {
+            dead = true;
+            break;
+          }
+        }
       }
 
       // last operator: diagonal of F * X; lane = column (l & 7) x k-partial (l >> 3)
-      {
+      if (!dead) {
         const int s = s_path[n - 1];
         const int d_in = s_dim[s];
         const int ld = (s_dim[s_path[n]] + 15) & ~15;
@@ -1087,9 +1220,332 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
           out.im = vi;
           out.e2 = (double)emax;
         }
+        if (lazy && lane == 0) {
+          const double a = hypot(out.re, out.im);
+          lazy_update(B, c, &ucur, a > 0.0 ? log(a) + out.e2 * 0.69314718055994530942 - R.L : -INFINITY);
+        }
       }
     }
     if (lane == 0) B.res[w] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// chain, streaming (sectors too large for an LDS-resident panel)
+// ---------------------------------------------------------------------------
+// One workgroup of 16 wavefronts per panel of 16 columns; the carried matrix
+// lives in a per-workgroup pair of global buffers (L2 resident).  Each
+// wavefront computes groups of kBigGroup 16-row tiles at a time over the
+// whole K range (operand B loaded once per group), applies the next
+// propagator and keeps a running per-column max; the column rescale of a
+// step is applied when the next step loads its operand (exact power of two,
+// exponents accumulated per column).
+constexpr int kBigWaves = 16;
+constexpr int kBigGroup = 4;
+
+__host__ __device__ constexpr size_t big_lds_bytes(int xr, int n_sec) {
+  return 8 * ((size_t)xr + 2 * kBigWaves * kPanel + kMaxOps + kPanel * 2) + 4 * (2 * (size_t)n_sec) +
+         2 * (2 * (size_t)kMaxOps + 2) + 64;
+}
+
+template <bool CPLX, bool LAZY>
+__global__ __launch_bounds__(kBigWaves * 64) void k_chain_big(DevImp I, BatchArgs B, double* xbuf) {
+  extern __shared__ double lds[];
+  constexpr int NT = kBigWaves * 64;
+  constexpr int GRP = CPLX ? 2 : kBigGroup;  // row tiles per pass (register budget)
+  const int XR = I.xrows;
+  const int NS = I.n_sec;
+  double* pb = lds;                          // [XR] propagator in front of the next operator
+  double* cmax = pb + XR;                    // [kBigWaves][16]
+  double* s_dt = cmax + kBigWaves * kPanel;  // [kMaxOps]
+  double* s_red = s_dt + kMaxOps;            // [2][16] close sums
+  double* cmaxi = s_red + 2 * kPanel;        // [kBigWaves][16] close partials, imaginary part
+  int* s_dim = (int*)(cmaxi + kBigWaves * kPanel);
+  int* s_eoff = s_dim + NS;
+  short* s_op = (short*)(s_eoff + NS);       // [kMaxOps]
+  short* s_path = s_op + kMaxOps;            // [kMaxOps + 1]
+  __shared__ long long s_w;
+  __shared__ int s_cexp[kPanel];             // accumulated power of two per column
+  __shared__ int s_pend[kPanel];             // rescale pending from the previous step
+  __shared__ double s_csq[kBigWaves][kPanel];  // lazy: per-wavefront column sums of squares
+  __shared__ int s_rej;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ln = lane & 15, lq = lane >> 4;
+  // this workgroup's buffers: two copies of X (re plane, then im plane)
+  const size_t plane = (size_t)XR * kPanel;
+  double* X0 = xbuf + (size_t)blockIdx.x * 2 * (CPLX ? 2 : 1) * plane;
+  double* X1 = X0 + (CPLX ? 2 : 1) * plane;
+
+  for (int i = tid; i < NS; i += NT) {
+    s_dim[i] = I.dim[i];
+    s_eoff[i] = I.eoff[i];
+  }
+  const long long total = B.cfg_off[B.n_cfg];
+  for (;;) {
+    if (tid == 0) s_w = (long long)atomicAdd(B.counter, 1u);
+    __syncthreads();
+    const long long w = s_w;
+    if (w >= total) break;
+    int lo = 0, hi = B.n_cfg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (B.cfg_off[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int c = lo;
+    const int local = (int)(w - B.cfg_off[c]);
+    const StrRec* recs = B.rec + (long long)c * NS;
+    lo = 0;
+    hi = NS - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (recs[mid].loc_off <= local) lo = mid; else hi = mid - 1;
+    }
+    const StrRec R = recs[lo];
+    const int col0 = (local - R.loc_off) * kPanel;
+    const int ncols = min(kPanel, R.width - col0);
+    const long long base = B.offsets[c];
+    const int n = (int)(B.offsets[c + 1] - base);
+    for (int t = tid; t < n; t += NT) {
+      const int p = (R.jstar + t) % n;
+      s_op[t] = (short)B.op[base + p];
+      s_dt[t] = p ? B.tau[base + p] - B.tau[base + p - 1] : B.tau[base] + I.beta - B.tau[base + n - 1];
+    }
+    if (tid < kPanel) {
+      s_cexp[tid] = 0;
+      s_pend[tid] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int q = R.q_start;
+      s_path[0] = (short)q;
+      for (int t = 0; t < n; ++t) {
+        q = I.next[q * I.nops + s_op[t]];
+        s_path[t + 1] = (short)q;
+      }
+    }
+    __syncthreads();
+
+    PanelRes out;
+    out.re = out.im = out.e2 = 0.0;
+    constexpr bool lazy = LAZY;
+    unsigned long long ucur = lazy ? lazy_initial(R, local) : 0;  // used by thread 0
+    bool dead = false;
+    if (n == 0) {
+      if (tid == 0) {
+        const double* e = I.esh + s_eoff[R.q_start];
+        double sum = 0.0;
+        for (int cc = 0; cc < ncols; ++cc) sum += exp(-I.beta * e[col0 + cc]);
+        out.re = sum;
+      }
+    } else {
+      double* Xin = X1;
+      double* Xout = X0;
+      for (int t = 0; t < n - 1; ++t) {
+        if (lazy) {
+          if (tid == 0) s_rej = lazy_rejected(B, c) ? 1 : 0;
+          __syncthreads();
+          if (s_rej) {
+            dead = true;
+            break;
+          }
+        }
+        const int s = s_path[t], s2 = s_path[t + 1];
+        const int d_in = s_dim[s], d_out = s_dim[s2];
+        const int ld = (d_out + 15) & ~15;
+        const int ntiles = ld >> 4;
+        const long long bo = I.boff[s * I.nops + s_op[t]];
+        const double* Fr = I.pool + bo;
+        const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
+        {
+          const double dt2 = s_dt[t + 1];
+          const double* e = I.esh + s_eoff[s2];
+          for (int r = tid; r < ld; r += NT) pb[r] = (r < d_out) ? exp(-dt2 * e[r]) : 0.0;
+        }
+        // scale of the input columns (rescale deferred from the previous step)
+        const double bsc = ldexp(1.0, -s_pend[ln]);
+        const double* e0 = I.esh + s_eoff[s];
+        const double p0 = (t == 0 && ln < ncols) ? exp(-s_dt[0] * e0[col0 + ln]) : 0.0;
+        __syncthreads();
+        double cm = 0.0, csq = 0.0;
+        for (int g0 = wave * GRP; g0 < ntiles; g0 += kBigWaves * GRP) {
+          dbl4 acc_r[GRP], acc_i[GRP];
+#pragma unroll
+          for (int g = 0; g < GRP; ++g) {
+            acc_r[g] = dbl4{0.0, 0.0, 0.0, 0.0};
+            acc_i[g] = dbl4{0.0, 0.0, 0.0, 0.0};
+          }
+          if (t == 0) {
+            if (ln < ncols) {
+              const int k = col0 + ln;
+#pragma unroll
+              for (int g = 0; g < GRP; ++g) {
+                if (g0 + g < ntiles) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    const long long a = (long long)k * ld + (g0 + g) * 16 + 4 * i + lq;
+                    acc_r[g][i] = Fr[a] * p0;
+                    if (CPLX) acc_i[g][i] = Fi[a] * p0;
+                  }
+                }
+              }
+            }
+          } else {
+            const int ksteps = (d_in + 3) >> 2;
+            for (int kc = 0; kc < ksteps; ++kc) {
+              const int krow = kc * 4 + lq;
+              const double br = Xin[krow * kPanel + ln] * bsc;
+              const double bi = CPLX ? Xin[plane + krow * kPanel + ln] * bsc : 0.0;
+#pragma unroll
+              for (int g = 0; g < GRP; ++g) {
+                if (g0 + g < ntiles) {
+                  const long long a = (long long)krow * ld + (g0 + g) * 16 + ln;
+                  const double ar = Fr[a];
+                  acc_r[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, acc_r[g], 0, 0, 0);
+                  if (CPLX) {
+                    const double ai = Fi[a];
+                    acc_r[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, acc_r[g], 0, 0, 0);
+                    acc_i[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acc_i[g], 0, 0, 0);
+                    acc_i[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acc_i[g], 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int g = 0; g < GRP; ++g) {
+            if (g0 + g < ntiles) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int m = (g0 + g) * 16 + 4 * i + lq;
+                const double p = pb[m];
+                const double vr = acc_r[g][i] * p;
+                Xout[m * kPanel + ln] = vr;
+                cm = fmax(cm, fabs(vr));
+                if (lazy) csq += vr * vr;
+                if (CPLX) {
+                  const double vi = acc_i[g][i] * p;
+                  Xout[plane + m * kPanel + ln] = vi;
+                  cm = fmax(cm, fabs(vi));
+                  if (lazy) csq += vi * vi;
+                }
+              }
+            }
+          }
+        }
+        cm = fmax(cm, __shfl_xor(cm, 16));
+        cm = fmax(cm, __shfl_xor(cm, 32));
+        csq += __shfl_xor(csq, 16);
+        csq += __shfl_xor(csq, 32);
+        if (lane < 16) {
+          cmax[wave * kPanel + lane] = cm;
+          s_csq[wave][lane] = csq;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid < kPanel) {
+          double M = 0.0, Q = 0.0;
+          for (int w2 = 0; w2 < kBigWaves; ++w2) {
+            M = fmax(M, cmax[w2 * kPanel + tid]);
+            Q += s_csq[w2][tid];
+          }
+          // lazy: log of this column's squared norm (X unscaled, exponents before this step)
+          if (lazy) s_red[tid] = Q > 0.0 ? log(Q) + 2.0 * s_cexp[tid] * 0.69314718055994530942 : -INFINITY;
+          int e = 0;
+          if (M > 0.0) frexp(M, &e);
+          s_pend[tid] = e;        // applied by the next load of X
+          s_cexp[tid] += e;
+        }
+        __syncthreads();
+        if (lazy && (t & 3) == 3) {
+          if (tid == 0) {
+            double mx = -INFINITY;
+            for (int j = 0; j < kPanel; ++j) mx = fmax(mx, s_red[j]);
+            int rj = 0;
+            if (mx > -INFINITY) {
+              double sum = 0.0;
+              for (int j = 0; j < kPanel; ++j) sum += exp(s_red[j] - mx);
+              const double logF2 = mx + log(sum);
+              rj = lazy_update(B, c, &ucur, 0.5 * (logF2 + log((double)ncols)) - R.L) ? 1 : 0;
+            }
+            s_rej = rj;
+          }
+          __syncthreads();
+          if (s_rej) {
+            dead = true;
+            break;
+          }
+        }
+        double* tmp = Xin;
+        Xin = Xout;
+        Xout = tmp;
+      }
+      // last operator: diagonal of F * (X * 2^-pend), rows col0 .. col0+ncols
+      if (!dead) {
+        const int s = s_path[n - 1];
+        const int d_in = s_dim[s];
+        const int ld = (s_dim[s_path[n]] + 15) & ~15;
+        const double* Fr = I.pool + I.boff[s * I.nops + s_op[n - 1]];
+        const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
+        const int cc = tid & 15;
+        const double bsc = ldexp(1.0, -s_pend[cc]);
+        double sr = 0.0, si = 0.0;
+        if (cc < ncols) {
+          for (int k = tid >> 4; k < d_in; k += NT / 16) {
+            const long long a = (long long)k * ld + col0 + cc;
+            const double fr = Fr[a], xr = Xin[k * kPanel + cc] * bsc;
+            if (CPLX) {
+              const double fi = Fi[a], xi = Xin[plane + k * kPanel + cc] * bsc;
+              sr += fr * xr - fi * xi;
+              si += fr * xi + fi * xr;
+            } else {
+              sr += fr * xr;
+            }
+          }
+        }
+        // reduce over the 64 k-partials of every column: wavefront, then LDS
+        for (int off = 16; off < 64; off <<= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (lane < 16) {
+          cmax[wave * kPanel + lane] = sr;
+          cmaxi[wave * kPanel + lane] = si;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int emax = INT_MIN;
+          for (int j = 0; j < ncols; ++j) {
+            double vr = 0.0, vi = 0.0;
+            for (int w2 = 0; w2 < kBigWaves; ++w2) {
+              vr += cmax[w2 * kPanel + j];
+              vi += cmaxi[w2 * kPanel + j];
+            }
+            s_red[j] = vr;
+            s_red[kPanel + j] = vi;
+            if (vr != 0.0 || vi != 0.0) emax = max(emax, s_cexp[j]);
+          }
+          if (emax != INT_MIN) {
+            double vr = 0.0, vi = 0.0;
+            for (int j = 0; j < ncols; ++j) {
+              const double f = ldexp(1.0, s_cexp[j] - emax);
+              vr += s_red[j] * f;
+              vi += s_red[kPanel + j] * f;
+            }
+            out.re = vr;
+            out.im = vi;
+            out.e2 = (double)emax;
+          }
+          if (lazy) {
+            const double a = hypot(out.re, out.im);
+            lazy_update(B, c, &ucur, a > 0.0 ? log(a) + out.e2 * 0.69314718055994530942 - R.L : -INFINITY);
+          }
+        }
+      }
+    }
+    if (tid == 0) B.res[w] = out;
+    __syncthreads();
   }
 }
 
@@ -1101,7 +1557,8 @@ __global__ __launch_bounds__(256) void k_combine(DevImp I, BatchArgs B) {
   if (c >= B.n_cfg) return;
   ctr_value v;
   v.re = v.im = v.log_scale = 0.0;
-  const int flags = B.cfg_flags[c];
+  int flags = B.cfg_flags[c];
+  if (B.log_thr != nullptr && B.cfg_rej[c]) flags |= CTR_FLAG_REJECTED;
   v.flags = flags;
   v.n_strings = B.cfg_nstr[c];
   v.log_bound = B.cfg_logB[c];
@@ -1233,11 +1690,17 @@ int wave_grid(const DevImp& imp, int device, size_t* lds_bytes) {
                                       : wave_lds_bytes<false>(imp.xrows, imp.n_sec, ne);
   if (lds_bytes) *lds_bytes = bytes;
   if (bytes > kMaxLds) return 0;
-  const void* fn = imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true>)
-                                  : reinterpret_cast<const void*>(&k_chain_wave<false>);
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, bytes) != hipSuccess) return 0;
+  const void* fns[2] = {imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true, false>)
+                                        : reinterpret_cast<const void*>(&k_chain_wave<false, false>),
+                        imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true, true>)
+                                        : reinterpret_cast<const void*>(&k_chain_wave<false, true>)};
+  int per_cu = 1 << 30;
+  for (const void* fn : fns) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
+    int k = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, fn, 256, bytes) != hipSuccess) return 0;
+    per_cu = std::min(per_cu, k);
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   return per_cu > 0 ? per_cu * cus : 0;
@@ -1248,10 +1711,48 @@ hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hi
   const int ne = imp.next_lds ? imp.n_sec * imp.nops : 0;
   bytes = imp.is_complex ? wave_lds_bytes<true>(imp.xrows, imp.n_sec, ne)
                          : wave_lds_bytes<false>(imp.xrows, imp.n_sec, ne);
-  const void* fn = imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true>)
-                                  : reinterpret_cast<const void*>(&k_chain_wave<false>);
+  const bool lazy = b.log_thr != nullptr;
+  const void* fn = imp.is_complex ? (lazy ? reinterpret_cast<const void*>(&k_chain_wave<true, true>)
+                                          : reinterpret_cast<const void*>(&k_chain_wave<true, false>))
+                                  : (lazy ? reinterpret_cast<const void*>(&k_chain_wave<false, true>)
+                                          : reinterpret_cast<const void*>(&k_chain_wave<false, false>));
   void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b)};
   return hipLaunchKernel(fn, dim3(grid), dim3(256), args, bytes, stream);
+}
+
+int big_grid(const DevImp& imp, int device, size_t* lds_bytes) {
+  const size_t bytes = big_lds_bytes(imp.xrows, imp.n_sec);
+  if (lds_bytes) *lds_bytes = bytes;
+  if (bytes > kMaxLds) return 0;
+  const void* fns[2] = {imp.is_complex ? reinterpret_cast<const void*>(&k_chain_big<true, false>)
+                                        : reinterpret_cast<const void*>(&k_chain_big<false, false>),
+                        imp.is_complex ? reinterpret_cast<const void*>(&k_chain_big<true, true>)
+                                        : reinterpret_cast<const void*>(&k_chain_big<false, true>)};
+  int per_cu = 1 << 30;
+  for (const void* fn : fns) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
+    int k = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, fn, kBigWaves * 64, bytes) != hipSuccess) return 0;
+    per_cu = std::min(per_cu, k);
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu > 0 ? per_cu * cus : 0;
+}
+
+size_t big_xbuf_doubles(const DevImp& imp, int grid) {
+  return (size_t)grid * 2 * (imp.is_complex ? 2 : 1) * (size_t)imp.xrows * kPanel;
+}
+
+hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf, int grid, hipStream_t stream) {
+  const size_t bytes = big_lds_bytes(imp.xrows, imp.n_sec);
+  const bool lazy = b.log_thr != nullptr;
+  const void* fn = imp.is_complex ? (lazy ? reinterpret_cast<const void*>(&k_chain_big<true, true>)
+                                          : reinterpret_cast<const void*>(&k_chain_big<true, false>))
+                                  : (lazy ? reinterpret_cast<const void*>(&k_chain_big<false, true>)
+                                          : reinterpret_cast<const void*>(&k_chain_big<false, false>));
+  void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b), &xbuf};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kBigWaves * 64), args, bytes, stream);
 }
 
 hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream) {

@@ -23,6 +23,10 @@ CTR_FP32_SPLIT = 1
 CTR_FLAG_ZERO = 1
 CTR_FLAG_REJECTED = 2
 CTR_FLAG_INVALID = 4
+CTR_KERNEL_AUTO = 0
+CTR_KERNEL_WAVE = 1
+CTR_KERNEL_BLOCK = 2
+CTR_KERNEL_STREAM = 3
 
 
 class ctr_value(ctypes.Structure):
@@ -31,7 +35,8 @@ class ctr_value(ctypes.Structure):
 
 
 class ctr_opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("slices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+    _fields_ = [("precision", ctypes.c_int32), ("slices", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ctr_impurity(ctypes.Structure):
@@ -123,9 +128,10 @@ def ctr_destroy(ctx) -> None:
     _lib.ctr_destroy(ctx)
 
 
-def _opts(precision):
+def _opts(precision, kernel=CTR_KERNEL_AUTO):
     o = ctr_opts()
     o.precision = int(precision)
+    o.kernel = int(kernel)
     return o
 
 
@@ -173,42 +179,43 @@ def _string_arrays(tau, op):
     return tau, op
 
 
-def ctr_trace(ctx, tau, op, precision=CTR_FP64):
+def ctr_trace(ctx, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     tau, op = _string_arrays(tau, op)
     v = ctr_value()
-    o = _opts(precision)
+    o = _opts(precision, kernel)
     _check(ctx, _lib.ctr_trace(ctx, int(op.size), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
                                ctypes.byref(o), ctypes.byref(v)))
     return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
 
 
-def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64):
+def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     tau, op = _string_arrays(tau, op)
     n = offsets.size - 1
     out = np.zeros(n, dtype=VALUE_DTYPE)
-    o = _opts(precision)
+    o = _opts(precision, kernel)
     _check(ctx, _lib.ctr_trace_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
                                      _ptr(op, ctypes.c_int32), ctypes.byref(o),
                                      out.ctypes.data_as(ctypes.POINTER(ctr_value))))
     return out
 
 
-def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64):
+def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64,
+                           kernel=CTR_KERNEL_AUTO):
     """Device pointers (ints); only enqueues on the context's stream."""
-    o = _opts(precision)
+    o = _opts(precision, kernel)
     _check(ctx, _lib.ctr_trace_batch_device(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
                                             ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
                                             ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
 
 
-def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP64):
+def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     tau, op = _string_arrays(tau, op)
     thr = np.ascontiguousarray(log_threshold, dtype=np.float64)
     n = offsets.size - 1
     out = np.zeros(n, dtype=VALUE_DTYPE)
-    o = _opts(precision)
+    o = _opts(precision, kernel)
     _check(ctx, _lib.ctr_trace_lazy_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
                                           _ptr(op, ctypes.c_int32), _ptr(thr, ctypes.c_double), ctypes.byref(o),
                                           out.ctypes.data_as(ctypes.POINTER(ctr_value))))
@@ -281,7 +288,9 @@ class TraceContext:
                 t = table.next[q, o]
                 if t >= 0:
                     blocks += ((int(d[t]) + 15) // 16 * 16) * ((int(d[q]) + 3) // 4 * 4) * es + 256
-        return int(blocks + (256 << 20))
+        xr = (int(d.max()) + 15) // 16 * 16
+        stream_buffers = 2 * (2 if table.is_complex else 1) * xr * 16 * 8 * 1024
+        return int(blocks + stream_buffers + (256 << 20))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -294,10 +303,10 @@ class TraceContext:
         except Exception:
             pass
 
-    def trace(self, tau, op, precision=CTR_FP64):
-        return ctr_trace(self.ctx, tau, op, precision)
+    def trace(self, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+        return ctr_trace(self.ctx, tau, op, precision, kernel)
 
-    def trace_batch(self, strings, precision=CTR_FP64):
+    def trace_batch(self, strings, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         """strings: sequence of (tau, op) pairs or objects with .tau and .op."""
         taus = [np.asarray(getattr(s, "tau", s[0] if isinstance(s, tuple) else None), dtype=np.float64)
                 for s in strings]
@@ -307,13 +316,13 @@ class TraceContext:
         offs[1:] = np.cumsum([o.size for o in ops])
         tau = np.concatenate(taus) if taus else np.zeros(0)
         op = np.concatenate(ops) if ops else np.zeros(0, np.int32)
-        return ctr_trace_batch(self.ctx, offs, tau, op, precision)
+        return ctr_trace_batch(self.ctx, offs, tau, op, precision, kernel)
 
-    def trace_packed(self, offsets, tau, op, precision=CTR_FP64):
-        return ctr_trace_batch(self.ctx, offsets, tau, op, precision)
+    def trace_packed(self, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+        return ctr_trace_batch(self.ctx, offsets, tau, op, precision, kernel)
 
-    def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64):
-        return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision)
+    def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+        return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision, kernel)
 
     def bound(self, tau, op) -> float:
         return ctr_bound(self.ctx, tau, op)

@@ -338,22 +338,100 @@ def test_lazy_bound_and_rejection(lib, ctx):
     thr = lb + rng.uniform(-3.0, 3.0, size=lb.size)
     out = c.lazy_batch(offs, tau, op, thr)
     rej = (out["flags"] & 2) != 0
-    assert np.array_equal(rej, (lb < thr) & (exact["n_strings"] > 0))
+    # everything below the plan bound is rejected; refined bounds reject more
+    assert np.all(rej[(lb < thr) & (exact["n_strings"] > 0)])
+    say(f"lazy: {int(np.sum(lb < thr))} rejected by the plan bound, {int(np.sum(rej))} in total")
     keep = ~rej
     assert np.array_equal(out["re"][keep], exact["re"][keep])
     assert np.array_equal(out["log_scale"][keep], exact["log_scale"][keep])
     # no false rejection: a rejected trace is truly below its threshold
     assert np.all(la[rej] < thr[rej])
+    assert np.all(out["re"][rej] == 0)
 
 
-def test_blocks_beyond_lds_limit_are_reported(lib, ctx):
-    from paper_2010_08482_amd.sectors import build_sectors
+@pytest.mark.parametrize("name,cid,count,kernel,split", [
+    ("dshell", 1, 300, "auto", False), ("dshell", 1, 200, "block", False), ("dshell", 1, 200, "block", True),
+    ("pshell", 2, 200, "auto", False), ("dd_fshell_n", 3, 12, "auto", False)])
+def test_lazy_refinement_rejects_only_below_threshold(lib, ctx, name, cid, count, kernel, split):
+    """Thresholds between |trace| and the plan bound: only the refined bounds
+    (Frobenius norm of the running product, exact panel values) can reject."""
+    k = {"auto": lib.CTR_KERNEL_AUTO, "block": lib.CTR_KERNEL_BLOCK}[kernel]
+    prec = lib.CTR_FP32_SPLIT if split else lib.CTR_FP64
+    tab, c = ctx(name)
+    imp = make_impurity(name)
+    strings = make_configs(cid, count) if name != "pshell" else \
+        [random_string(np.random.Generator(np.random.PCG64(100 + i)), imp.n_flavors, imp.beta, 40, "alternating")
+         for i in range(count)]
+    offs, tau, op = pack(strings)
+    say(f"[gpu] lazy refinement {name} x{count} kernel={kernel} split={split}")
+    exact = c.trace_packed(offs, tau, op, prec, k)
+    la = np.array([lib.log_abs(v) for v in exact])
+    lb = exact["log_bound"]
+    live = np.isfinite(la)
+    rng = np.random.Generator(np.random.PCG64(21))
+    thr = np.where(live, la + rng.uniform(0.0, 1.0, size=la.size) * (lb - la), -np.inf)
+    thr = np.where(rng.uniform(size=la.size) < 0.5, thr, la - 1.0)   # half of them must be kept
+    out = c.lazy_batch(offs, tau, op, thr, prec, k)
+    rej = (out["flags"] & 2) != 0
+    assert np.all(la[rej] < thr[rej])            # no false rejection
+    keep = ~rej
+    assert np.array_equal(out["re"][keep], exact["re"][keep])
+    assert not np.any(rej & (thr < la))
+    say(f"lazy refinement {name}: {int(np.sum(rej))} of {int(np.sum(thr > la))} rejectable configurations rejected")
 
-    tab = build_sectors(make_impurity("dd_fshell_n"))
-    assert tab.max_dim == 3432
-    say("[gpu] ctr_set_impurity with 3432-dim sectors")
+
+@pytest.mark.parametrize("kernel", ["wave", "block", "stream"])
+def test_every_chain_kernel_matches_the_oracle(lib, ctx, kernel):
+    """The three chain kernels (wavefront, LDS workgroup, streaming) forced on
+    impurities the oracle covers."""
+    k = {"wave": lib.CTR_KERNEL_WAVE, "block": lib.CTR_KERNEL_BLOCK, "stream": lib.CTR_KERNEL_STREAM}[kernel]
+    g = load_golden("dshell_config1")
+    tab, c = ctx("dshell")
+    recs = g["records"][:96]
+    say(f"[gpu] kernel={kernel} dshell x{len(recs)}")
+    out = c.trace_batch(make_configs(1, len(recs)), kernel=k)
+    check_against(out, [golden_pair(r) for r in recs], [(r["abs"], r["abs_log"]) for r in recs], f"dshell {kernel}")
+    for name in ("pshell_random", "dshell_so_random"):
+        g = load_golden(name)
+        tab, c = ctx(g["impurity"])
+        strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
+        say(f"[gpu] kernel={kernel} {name}")
+        out = c.trace_batch(strings, kernel=k)
+        check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                      f"{name} {kernel}")
+
+
+def test_kernel_option_errors(lib, ctx):
+    tab, c = ctx("dshell")
     with pytest.raises(lib.CtraceError) as e:
-        lib.TraceContext(tab, arena_bytes=1 << 30)
+        c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_WAVE)
+    assert e.value.status == -7
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_STREAM)
+    assert e.value.status == -7
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace([0.5, 1.0], [1, 0], kernel=7)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("phase_seed", [None, 11])
+def test_sectors_of_3432_states_density_density_vs_enumeration(lib, ctx, phase_seed):
+    """N-only sectors of the 14-flavor shell (largest 3432 states): the
+    streaming kernel, checked against exact state enumeration."""
+    from oracle import densdens_trace
+
+    tab, c = ctx("dd_fshell_n", phase_seed)
+    assert tab.max_dim == 3432
+    imp = make_impurity("dd_fshell_n")
+    cfgs = make_configs(3, 10)  # 14 flavors, beta 40, orders 60..200
+    say(f"[gpu] ctr_trace_batch dd_fshell_n phase={phase_seed} x{len(cfgs)}")
+    out = c.trace_batch(cfgs)
+    refs = [densdens_trace(imp, s.tau, s.op) for s in cfgs]
+    scales = [densdens_trace(imp, s.tau, s.op, moduli=True) for s in cfgs]
+    check_against(out, refs, scales, f"dd_fshell_n phase={phase_seed}")
+    assert sum(1 for r in refs if r[0] != 0) >= 5
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace(cfgs[0].tau, cfgs[0].op, kernel=lib.CTR_KERNEL_BLOCK)
     assert e.value.status == -7
 
 

@@ -147,3 +147,23 @@ def test_config_strings(cid):
             assert np.sum(ops_f % 2 == 1) == np.sum(ops_f % 2 == 0)
             if spec.rule == "alternating":
                 assert np.all(np.diff(ops_f % 2) != 0)
+
+
+def test_insert_pair_keeps_flavors_alternating():
+    from workloads.configs import insert_pair
+    from workloads.impurity import IMPURITY_SHAPE
+
+    for cid, name in ((1, "dshell"), (3, "fshell_cf")):
+        nf, beta = IMPURITY_SHAPE[name]
+        rng = np.random.Generator(np.random.PCG64(77))
+        for s in make_configs(cid, 100):
+            p = insert_pair(rng, s, nf, beta)
+            assert p.n == s.n + 2
+            assert np.all(np.diff(p.tau) >= 0) and np.all((p.tau >= 0) & (p.tau < beta))
+            for f in range(nf):
+                k = p.op[(p.op >> 1) == f] & 1
+                if k.size:
+                    assert np.all(k[1:] != k[:-1]) and k[0] != k[-1]
+            # the old string is a subsequence of the new one
+            keep = np.isin(p.tau, s.tau)
+            assert np.array_equal(p.op[keep], s.op)

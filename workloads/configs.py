@@ -105,3 +105,33 @@ def pack(strings: list[OperatorString]):
     tau = np.concatenate([s.tau for s in strings]) if strings else np.zeros(0)
     op = np.concatenate([s.op for s in strings]).astype(np.int32) if strings else np.zeros(0, np.int32)
     return offs, np.ascontiguousarray(tau, dtype=np.float64), np.ascontiguousarray(op, dtype=np.int32)
+
+
+def insert_pair(rng: np.random.Generator, s: OperatorString, n_flavors: int, beta: float) -> OperatorString:
+    """Proposal of the Markov chain's pair insertion (App. D): a flavor f and a
+    time ta are drawn uniformly, tb uniformly in the stretch from ta to the next
+    operator of flavor f (cyclically, wrapping at beta), and the pair goes in
+    with the types that keep flavor f alternating: a creator first where f is
+    empty at ta, an annihilator first where it is occupied (either, at random,
+    where f has no operator yet)."""
+    f = int(rng.integers(n_flavors))
+    ta = float(rng.uniform(0.0, beta))
+    mine = s.tau[(s.op >> 1) == f]
+    kinds = s.op[(s.op >> 1) == f] & 1
+    if mine.size == 0:
+        gap = beta
+        occupied = bool(rng.integers(2))
+    else:
+        after = np.nonzero(mine > ta)[0]
+        j = int(after[0]) if after.size else 0
+        gap = (mine[j] - ta) if after.size else (mine[0] + beta - ta)
+        occupied = kinds[j] == 0  # the next operator of f removes an electron
+    tb = ta + float(rng.uniform(0.0, gap))
+    if tb >= beta:
+        tb -= beta
+    first = 2 * f + (0 if occupied else 1)
+    second = 2 * f + (1 if occupied else 0)
+    tau = np.concatenate([s.tau, [ta, tb]])
+    op = np.concatenate([s.op, np.array([first, second], dtype=np.int32)])
+    order = np.argsort(tau, kind="stable")
+    return OperatorString(tau[order].astype(np.float64), op[order].astype(np.int32))
