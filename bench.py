@@ -69,11 +69,15 @@ def algorithmic_flops(tab, strings):
     return total
 
 
-def chain_kernel_name(tab):
-    """Kernel the library's automatic choice runs for FP64 traces of this table:
-    the wavefront kernel for sectors of at most 128 states, the LDS workgroup
-    kernel while a 16-column panel fits LDS, the streaming kernel beyond."""
+def chain_kernel_name(tab, n_cfg):
+    """Kernel the library's automatic choice runs for a batch of FP64 traces of
+    this table: block-grouped rounds for batches of at least 256 traces with
+    sectors of at most 384 states, else the wavefront kernel for sectors of at
+    most 128 states, the LDS workgroup kernel while a 16-column panel fits LDS,
+    the streaming kernel beyond."""
     xr = (tab.max_dim + 15) // 16 * 16
+    if n_cfg >= 256 and xr <= 384:
+        return "k_gstep"
     if xr <= 128:
         return "k_chain_wave"
     if xr <= (576 if tab.is_complex else 1024):
@@ -185,7 +189,10 @@ def main():
     print(f"[bench] workload {wl['name']}: {n_cfg} configurations, {tab.n_sectors} sectors, "
           f"largest block {tab.max_dim}", file=sys.stderr, flush=True)
 
-    ctx = ctrace.TraceContext(tab)
+    # per-call scratch: the grouped rounds keep every surviving string's carried
+    # matrix resident, so give the arena half of the free device memory (at most 64 GiB)
+    free, _ = torch.cuda.mem_get_info(0)
+    ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
     offs, tau, op = pack(strings)
     dev = "cuda:0"
     d_offs = torch.from_numpy(offs).to(dev)
@@ -250,13 +257,13 @@ def main():
         rel_s = np.array(rel_s)
         split = {"value": n_cfg * ks / el_s, "unit": "trace evals/s", "steps": ks, "ms_per_step": el_s / ks * 1e3,
                  "slice_bits": 8, "slices": 6, "fp32_products_per_fma": 21,
-                 "launch_ms": ms_s / max(n_s, 1),
+                 "launch_ms": ms_s / max(n_s, 1), "chain_ms_per_step": ms_s / ks,
                  "rel_err_vs_fp64": {"p50": float(np.percentile(rel_s, 50)), "p99": float(np.percentile(rel_s, 99)),
                                      "max": float(rel_s.max())} if rel_s.size else None}
 
     flops = algorithmic_flops(tab, strings)
-    if split is not None and split["launch_ms"] > 0:
-        per = flops / (split["launch_ms"] * 1e-3) / 1e12 / max(launches / max(args.steps, 1), 1)
+    if split is not None and split["chain_ms_per_step"] > 0:
+        per = flops / (split["chain_ms_per_step"] * 1e-3) / 1e12
         split["achieved_fp64_equivalent_tflops"] = per
         split["executed_fp32_tflops"] = 21 * per
         split["frac_fp32_peak"] = 21 * per / 157.3
@@ -315,8 +322,8 @@ def main():
                    "complex": bool(tab.is_complex), "precision": "FP64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": measured_traffic(chain_kernel_name(tab)),
-                     "kernel": chain_kernel_name(tab), "algorithmic_flop_per_launch": flops / launches_per_step,
+                     "traffic": measured_traffic(chain_kernel_name(tab, n_cfg)),
+                     "kernel": chain_kernel_name(tab, n_cfg), "algorithmic_flop_per_launch": flops / launches_per_step,
                      "launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

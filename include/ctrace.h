@@ -77,11 +77,17 @@ typedef struct {
 
 /* ctr_opts.kernel: which chain kernel runs the block products */
 enum {
-  CTR_KERNEL_AUTO = 0,    /* wavefront kernel for sectors <= 128 states (FP64), else the
-                             LDS-resident workgroup kernel when the panel fits LDS, else streaming */
+  CTR_KERNEL_AUTO = 0,    /* batches of >= 256 FP64 non-lazy traces: the block-grouped rounds when
+                             the sectors fit them and the arena holds their scratch; otherwise the
+                             wavefront kernel for sectors <= 128 states (FP64), else the LDS-resident
+                             workgroup kernel when the panel fits LDS, else streaming */
   CTR_KERNEL_WAVE = 1,    /* one wavefront per 8-column panel; sectors <= 128 states, FP64 only */
   CTR_KERNEL_BLOCK = 2,   /* one workgroup per 16-column panel, X in LDS (<= 1024 real / 576 complex) */
-  CTR_KERNEL_STREAM = 3   /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
+  CTR_KERNEL_STREAM = 3,  /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
+  CTR_KERNEL_GROUPED = 4  /* block-grouped rounds: all strings of the batch advance one operator per
+                             round and the strings at the same block share one wide product; sectors
+                             <= 384 states, FP64, not lazy.  Synchronises the stream once per batch
+                             (to size its scratch from the number of surviving strings) */
 };
 
 typedef struct {
@@ -190,8 +196,11 @@ ctr_status ctr_trace_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, 
 
 /*
  * Same as ctr_trace_batch with every array already in device memory
- * (d_offsets[n_cfg+1], d_tau, d_op, d_out[n_cfg]); only enqueues work on
- * the context's stream.  Validation happens on the device: an invalid
+ * (d_offsets[n_cfg+1], d_tau, d_op, d_out[n_cfg]); enqueues work on the
+ * context's stream and returns without waiting, except that the
+ * block-grouped kernel (CTR_KERNEL_GROUPED, or AUTO choosing it) waits once
+ * per chunk for the number of surviving strings, which sizes its scratch.
+ * Validation happens on the device: an invalid
  * configuration gets CTR_FLAG_INVALID and re = im = 0.  Errors:
  * CTR_ERR_OOM (per-call scratch does not fit; the call is split into
  * chunks first, so this means even one configuration does not fit),

@@ -45,7 +45,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
     objs = []
-    for src, extra in (("ctrace_kernels.hip", ["-x", "hip"]), ("ctrace_host.cpp", ["-x", "hip"])):
+    for src, extra in (("ctrace_kernels.hip", ["-x", "hip"]), ("ctrace_group.hip", ["-x", "hip"]),
+                       ("ctrace_host.cpp", ["-x", "hip"])):
         obj = os.path.join(BUILD, src + ".o")
         _run([cc, *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(SRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -1,0 +1,733 @@
+// Block-grouped evaluation of a batch of traces (gfx950).
+//
+// Every surviving sector string (Sec. 3.3.1) is a chain X <- F_op(q) P X over
+// its start sector's columns.  Strings are independent, so instead of running
+// each string's whole chain alone (re-reading each operator block once per
+// string), all strings of the batch advance one operator per round, and in
+// every round the strings standing at the same block F_op(q) are grouped:
+// their columns are packed side by side and multiplied by F in one wide
+// FP64 MFMA product, so each block is read once per 32 or 64 columns.
+//
+//   k_gstrings  one thread per surviving string: configuration and record
+//   k_gscan1    one workgroup: column offsets of the strings (exclusive scan
+//               of their widths), total columns, number of rounds
+//   k_gwalk     one thread per string: walks its rotated sector path and
+//               counts, per (round, block), strings and columns
+//   k_gsched    one workgroup per round: group offsets and work items
+//   k_gwalk     (again) one thread per string: its position in every round's groups
+//   k_gcolpref  one workgroup per round: column offsets in group order
+//   k_gscan2    one workgroup: offsets of every round's columns and items
+//   k_gkeys     one thread per (round, group): the group of every work item
+//   k_gitems    one thread per (round, string): global column and gap of
+//               every column-step, in group order (work items read them
+//               with one coalesced load instead of searching)
+//   k_gfirst    one workgroup per string: the first operator (a column-scaled
+//               copy of F, the carried matrix starts as the identity)
+//   k_gstep     persistent, one launch per round: work items of 64 (real) or
+//               32 (complex) columns of one group, F * X on FP64 MFMA 16x16x4
+//               with the propagator of the next gap and the per-column
+//               power-of-two rescale fused into the epilogue; strings at
+//               their last operator only form the diagonal of F * X
+//   k_gcombine  one wavefront per configuration: (mantissa, exponent) merge
+//               of all columns of all its strings
+#include <math.h>
+
+#include "ctrace_internal.h"
+
+namespace ctr {
+
+namespace {
+
+__device__ __forceinline__ double gap_before(const double* tau, int n, int p, double beta) {
+  // imaginary-time gap in front of operator p; position 0 carries the wrap gap
+  return p ? tau[p] - tau[p - 1] : tau[0] + beta - tau[n - 1];
+}
+
+// Largest i in [lo, hi) with a[i] <= x (a non-decreasing, a[lo] <= x).
+template <typename T>
+__device__ __forceinline__ int last_le(const T* a, int lo, int hi, T x) {
+  hi -= 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Block-wide exclusive scan of v over the calling workgroup (blockDim.x
+// threads, at most 1024); returns the exclusive prefix, *total the sum.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* s_tmp, T* total) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  s_tmp[t] = v;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const T u = (t >= off) ? s_tmp[t - off] : T(0);
+    __syncthreads();
+    s_tmp[t] += u;
+    __syncthreads();
+  }
+  const T incl = s_tmp[t];
+  *total = s_tmp[nt - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// strings of the batch
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gstrings(DevImp I, BatchArgs B, GroupArgs G) {
+  const long long w = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long S = B.cfg_off[B.n_cfg];
+  if (w >= S) return;
+  const int c = last_le<long long>(B.cfg_off, 0, B.n_cfg, w);
+  const int local = (int)(w - B.cfg_off[c]);
+  const StrRec* recs = B.rec + (long long)c * I.n_sec;
+  int lo = 0, hi = I.n_sec - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (recs[mid].loc_off <= local) lo = mid; else hi = mid - 1;
+  }
+  G.s_cfg[w] = c;
+  G.s_rec[w] = lo;
+  G.s_width[w] = recs[lo].width;
+  G.s_n[w] = (int)(B.offsets[c + 1] - B.offsets[c]);
+}
+
+__global__ __launch_bounds__(1024) void k_gscan1(DevImp I, BatchArgs B, GroupArgs G) {
+  __shared__ long long s_tmp[1024];
+  __shared__ long long s_cs[1024], s_ns[1024];
+  __shared__ int s_max[1024];
+  const int t = threadIdx.x;
+  const long long S = B.cfg_off[B.n_cfg];
+  const long long chunk = (S + 1023) / 1024;
+  const long long lo = min((long long)t * chunk, S), hi = min(lo + chunk, S);
+  long long sum = 0, cs = 0, ns = 0;
+  int nmax = 0;
+  for (long long w = lo; w < hi; ++w) {
+    const int wd = G.s_width[w], n = G.s_n[w];
+    sum += wd;
+    cs += (long long)wd * max(n - 1, 0);
+    ns += max(n - 1, 0);
+    nmax = max(nmax, n);
+  }
+  long long total = 0;
+  long long run = block_exclusive_scan<long long>(sum, s_tmp, &total);
+  for (long long w = lo; w < hi; ++w) {
+    G.s_colbase[w] = run;
+    run += G.s_width[w];
+  }
+  s_max[t] = nmax;
+  s_cs[t] = cs;
+  s_ns[t] = ns;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) {
+      s_max[t] = max(s_max[t], s_max[t + off]);
+      s_cs[t] += s_cs[t + off];
+      s_ns[t] += s_ns[t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    G.info[0] = S;
+    G.info[1] = total;
+    G.info[2] = s_max[0];  // rounds: the close of a string of n operators is round n - 1
+    G.info[3] = s_cs[0];
+    // work items: at most one partial item per (round, group) on top of the full ones
+    G.info[4] = s_cs[0] / min(G.cw_step, G.cw_close) + s_ns[0] + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// schedule
+// ---------------------------------------------------------------------------
+// Group key of a string at round r >= 1: the block it applies, offset by NB
+// at its last operator (the close).
+__global__ __launch_bounds__(256) void k_gwalk(DevImp I, BatchArgs B, GroupArgs G, int scatter) {
+  const long long w = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (w >= G.S) return;
+  const int c = G.s_cfg[w];
+  const StrRec R = B.rec[(long long)c * I.n_sec + G.s_rec[w]];
+  const long long base = B.offsets[c];
+  const int n = (int)(B.offsets[c + 1] - base);
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  int cur = R.q_start;
+  for (int r = 0; r < n; ++r) {
+    const int op = B.op[base + (R.jstar + r) % n];
+    const int blk = cur * I.nops + op;
+    if (r >= 1) {
+      const int key = (r < n - 1) ? blk : NB + blk;
+      const long long rk = (long long)r * NK + key;
+      if (!scatter) {
+        atomicAdd(G.hist + rk, 1);
+        atomicAdd(G.hcols + rk, R.width);
+      } else {
+        const int pos = G.gstart[(long long)r * (NK + 1) + key] + atomicAdd(G.cursor + rk, 1);
+        G.sorted[(long long)r * G.S + pos] = (int)w;
+      }
+    }
+    cur = I.next[blk];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_gsched(DevImp I, GroupArgs G) {
+  __shared__ int s_tmp[1024];
+  const int r = blockIdx.x + 1;
+  if (r >= G.R) return;
+  const int t = threadIdx.x;
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  const int chunk = (NK + 1023) / 1024;
+  const int lo = min(t * chunk, NK), hi = min(lo + chunk, NK);
+  const int* hist = G.hist + (long long)r * NK;
+  const int* hcols = G.hcols + (long long)r * NK;
+  int* gstart = G.gstart + (long long)r * (NK + 1);
+  int* istart = G.istart + (long long)r * (NK + 1);
+  int s1 = 0, s2 = 0;
+  for (int k = lo; k < hi; ++k) {
+    s1 += hist[k];
+    s2 += (hcols[k] + (k < NB ? G.cw_step : G.cw_close) - 1) / (k < NB ? G.cw_step : G.cw_close);
+  }
+  int tot1 = 0, tot2 = 0;
+  int run1 = block_exclusive_scan<int>(s1, s_tmp, &tot1);
+  int run2 = block_exclusive_scan<int>(s2, s_tmp, &tot2);
+  for (int k = lo; k < hi; ++k) {
+    gstart[k] = run1;
+    istart[k] = run2;
+    run1 += hist[k];
+    run2 += (hcols[k] + (k < NB ? G.cw_step : G.cw_close) - 1) / (k < NB ? G.cw_step : G.cw_close);
+  }
+  if (t == 0) {
+    gstart[NK] = tot1;
+    istart[NK] = tot2;
+    G.n_items[r] = tot2;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_gcolpref(DevImp I, BatchArgs B, GroupArgs G) {
+  __shared__ int s_tmp[1024];
+  const int r = blockIdx.x + 1;
+  if (r >= G.R) return;
+  const int t = threadIdx.x;
+  const int NK = 2 * I.n_sec * I.nops;
+  const int cnt = G.gstart[(long long)r * (NK + 1) + NK];
+  const int chunk = (cnt + 1023) / 1024;
+  const int lo = min(t * chunk, cnt), hi = min(lo + chunk, cnt);
+  const int* sorted = G.sorted + (long long)r * G.S;
+  int* colpref = G.colpref + (long long)r * G.S;
+  int sum = 0;
+  for (int p = lo; p < hi; ++p) sum += G.s_width[sorted[p]];
+  int tot = 0;
+  int run = block_exclusive_scan<int>(sum, s_tmp, &tot);
+  for (int p = lo; p < hi; ++p) {
+    colpref[p] = run;
+    run += G.s_width[sorted[p]];
+  }
+  if (t == 0) G.rcols[r] = tot;
+}
+
+// Offsets of every round's column-steps and work items (rounds 1 .. R-1).
+__global__ __launch_bounds__(1024) void k_gscan2(GroupArgs G) {
+  __shared__ long long s_tmp[1024];
+  const int t = threadIdx.x;
+  const int chunk = (G.R + 1023) / 1024;
+  const int lo = min(t * chunk, G.R), hi = min(lo + chunk, G.R);
+  long long c = 0, it = 0;
+  for (int r = lo; r < hi; ++r) {
+    c += r >= 1 ? G.rcols[r] : 0;
+    it += r >= 1 ? G.n_items[r] : 0;
+  }
+  long long tot = 0;
+  long long rc = block_exclusive_scan<long long>(c, s_tmp, &tot);
+  long long ri = block_exclusive_scan<long long>(it, s_tmp, &tot);
+  for (int r = lo; r < hi; ++r) {
+    G.rcoloff[r] = rc;
+    G.ritemoff[r] = ri;
+    rc += r >= 1 ? G.rcols[r] : 0;
+    ri += r >= 1 ? G.n_items[r] : 0;
+  }
+}
+
+// Group of every work item of round r.
+__global__ __launch_bounds__(256) void k_gkeys(DevImp I, GroupArgs G) {
+  const int NK = 2 * I.n_sec * I.nops;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long long)(G.R - 1) * NK) return;
+  const int r = (int)(idx / NK) + 1, key = (int)(idx % NK);
+  const int* istart = G.istart + (long long)r * (NK + 1);
+  int* out = G.item_key + G.ritemoff[r];
+  for (int it = istart[key]; it < istart[key + 1]; ++it) out[it] = key;
+}
+
+// Column-steps of round r in group order: global column and the gap in front
+// of the string's next operator (or, at its last operator, the column's index
+// in the start sector, where the diagonal is taken).
+__global__ __launch_bounds__(256) void k_gitems(DevImp I, BatchArgs B, GroupArgs G) {
+  const int NK = 2 * I.n_sec * I.nops;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long long)(G.R - 1) * G.S) return;
+  const int r = (int)(idx / G.S) + 1;
+  const int p = (int)(idx % G.S);
+  if (p >= G.gstart[(long long)r * (NK + 1) + NK]) return;
+  const int w = G.sorted[(long long)r * G.S + p];
+  const int n = G.s_n[w], width = G.s_width[w];
+  const long long cb = G.s_colbase[w];
+  const long long base = G.rcoloff[r] + G.colpref[(long long)r * G.S + p];
+  if (r == n - 1) {
+    for (int j = 0; j < width; ++j) {
+      G.colg[base + j] = (int)(cb + j);
+      G.colaux[base + j] = (double)j;
+    }
+  } else {
+    const int c = G.s_cfg[w];
+    const StrRec R = B.rec[(long long)c * I.n_sec + G.s_rec[w]];
+    const long long o = B.offsets[c];
+    const double dt = gap_before(B.tau + o, n, (R.jstar + r + 1) % n, I.beta);
+    for (int j = 0; j < width; ++j) {
+      G.colg[base + j] = (int)(cb + j);
+      G.colaux[base + j] = dt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// round 0: the first operator of every string
+// ---------------------------------------------------------------------------
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_gfirst(DevImp I, BatchArgs B, GroupArgs G) {
+  const long long w = blockIdx.x;
+  if (w >= G.S) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = G.s_cfg[w];
+  const StrRec R = B.rec[(long long)c * I.n_sec + G.s_rec[w]];
+  const long long base = B.offsets[c];
+  const int n = (int)(B.offsets[c + 1] - base);
+  const long long cb = G.s_colbase[w];
+  const int s = R.q_start;
+  const double* e_s = I.esh + I.eoff[s];
+  if (n == 0) {
+    // partition-function string: trace of the diagonal propagator
+    for (int j = threadIdx.x; j < R.width; j += 256) {
+      PanelRes o;
+      o.re = exp(-I.beta * e_s[j]);
+      o.im = 0.0;
+      o.e2 = 0.0;
+      G.colres[cb + j] = o;
+    }
+    return;
+  }
+  const double* tau = B.tau + base;
+  const int op0 = B.op[base + R.jstar];
+  const int blk = s * I.nops + op0;
+  const int s2 = I.next[blk];
+  const int d_out = I.dim[s2];
+  const int ld = (d_out + 15) & ~15;
+  const double* Fr = I.pool + I.boff[blk];
+  const double* Fi = Fr + (long long)ld * ((I.dim[s] + 3) & ~3);
+  const double dt0 = gap_before(tau, n, R.jstar, I.beta);
+  const double dt1 = gap_before(tau, n, (R.jstar + 1) % n, I.beta);
+  const double* e_2 = I.esh + I.eoff[s2];
+  const long long plane = G.T * (long long)I.xrows;
+  double* X = G.X[0];
+  for (int j = wave; j < R.width; j += 4) {
+    const double p0 = exp(-dt0 * e_s[j]);
+    double vr[8], vi[8];
+    double cm = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = lane + 64 * u;
+      vr[u] = vi[u] = 0.0;
+      if (m < d_out) {
+        const double p = p0 * exp(-dt1 * e_2[m]);
+        vr[u] = Fr[(long long)j * ld + m] * p;
+        cm = fmax(cm, fabs(vr[u]));
+        if (CPLX) {
+          vi[u] = Fi[(long long)j * ld + m] * p;
+          cm = fmax(cm, fabs(vi[u]));
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off));
+    int e = 0;
+    if (cm > 0.0) frexp(cm, &e);
+    const double sc = ldexp(1.0, -e);
+    double* col = X + (cb + j) * I.xrows;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = lane + 64 * u;
+      if (m < ld) {
+        col[m] = vr[u] * sc;
+        if (CPLX) col[plane + m] = vi[u] * sc;
+      }
+    }
+    if (lane == 0) G.colexp[cb + j] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rounds r >= 1
+// ---------------------------------------------------------------------------
+template <bool CPLX, int NW, int RT, int CT>
+__global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupArgs G, int r) {
+  constexpr int CW = CT * 16;            // columns per work item
+  constexpr int NT = NW * 64;
+  constexpr int KC = 64;                 // rows of X staged in LDS per chunk
+  constexpr int LDB = KC + 1;            // odd stride: the 16 columns of a B fragment hit distinct banks
+  constexpr int PL = CPLX ? 2 : 1;
+  __shared__ double sB[PL * CW * LDB];
+  __shared__ double s_cmax[NW * CW];
+  __shared__ double s_dt[CW];
+  __shared__ long long s_gcol[CW];
+  __shared__ int s_e[CW];
+  __shared__ int s_item;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  const int XR = I.xrows;
+  const long long plane = G.T * (long long)XR;
+  const double* Xin = G.X[(r + 1) & 1];
+  double* Xout = G.X[r & 1];
+  const int n_items = G.n_items[r];
+  const int* istart = G.istart + (long long)r * (NK + 1);
+  const int* gstart = G.gstart + (long long)r * (NK + 1);
+  const int* hcols = G.hcols + (long long)r * NK;
+  const int* colpref = G.colpref + (long long)r * G.S;
+
+  const long long* ritemoff = G.ritemoff;
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(G.counters + r, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= n_items) break;
+    // group and column range of this item
+    const int key = G.item_key[ritemoff[r] + item];
+    const bool close = key >= NB;
+    const int blk = close ? key - NB : key;
+    const int cw = close ? G.cw_close : CW;
+    const int c0 = (item - istart[key]) * cw;
+    const int ncol = min(cw, hcols[key] - c0);
+    const long long relbase = G.rcoloff[r] + colpref[gstart[key]] + c0;
+    const int s = blk / I.nops;
+    const int s2 = I.next[blk];
+    const int d_in = I.dim[s], d_out = I.dim[s2];
+    const int ld = (d_out + 15) & ~15;
+    const int kp = (d_in + 3) & ~3;
+    const double* Fr = I.pool + I.boff[blk];
+    const double* Fi = Fr + (long long)ld * kp;
+
+    if (close) {
+      // diagonal of F * X: column j of the string meets row j of F
+      for (int j = wave; j < ncol; j += NW) {
+        const long long gcol = G.colg[relbase + j];
+        const int jj = (int)G.colaux[relbase + j];
+        const double* xr = Xin + gcol * XR;
+        double sr = 0.0, si = 0.0;
+        for (int k = lane; k < d_in; k += 64) {
+          const double fr = Fr[(long long)k * ld + jj], x = xr[k];
+          if (CPLX) {
+            const double fi = Fi[(long long)k * ld + jj], xi = xr[plane + k];
+            sr += fr * x - fi * xi;
+            si += fr * xi + fi * x;
+          } else {
+            sr += fr * x;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (lane == 0) {
+          PanelRes o;
+          o.re = sr;
+          o.im = si;
+          o.e2 = (double)G.colexp[gcol];
+          G.colres[gcol] = o;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // columns of this item: global column, next gap
+    if (tid < CW) {
+      s_gcol[tid] = tid < ncol ? (long long)G.colg[relbase + tid] : -1;
+      s_dt[tid] = tid < ncol ? G.colaux[relbase + tid] : 0.0;
+    }
+
+    typedef double dbl4 __attribute__((ext_vector_type(4)));
+    dbl4 acc_r[RT][CT], acc_i[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        acc_r[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acc_i[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+      }
+    const int ntiles = ld >> 4;
+    // A fragments of the next k-step are loaded while the current one multiplies
+    double nr[RT], ni[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int tile = wave + i * NW;
+      nr[i] = ni[i] = 0.0;
+      if (tile < ntiles) {
+        const long long a = (long long)lq * ld + tile * 16 + ln;
+        nr[i] = Fr[a];
+        if (CPLX) ni[i] = Fi[a];
+      }
+    }
+    for (int k0 = 0; k0 < kp; k0 += KC) {
+      const int kc = min(KC, kp - k0);
+      __syncthreads();  // previous chunk consumed; s_gcol visible
+      for (int idx = tid; idx < CW * kc; idx += NT) {
+        const int j = idx / kc, kk = idx - j * kc;
+        const long long g = s_gcol[j];
+        const long long a = g * XR + k0 + kk;
+        sB[j * LDB + kk] = g >= 0 ? Xin[a] : 0.0;
+        if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] : 0.0;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < kc; kk += 4) {
+        double ar[RT], ai[RT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          ar[i] = nr[i];
+          ai[i] = ni[i];
+        }
+        const int kn = k0 + kk + 4;
+        if (kn < kp) {
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            const int tile = wave + i * NW;
+            if (tile < ntiles) {
+              const long long a = (long long)(kn + lq) * ld + tile * 16 + ln;
+              nr[i] = Fr[a];
+              if (CPLX) ni[i] = Fi[a];
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+          const double br = sB[(t * 16 + ln) * LDB + kk + lq];
+          const double bi = CPLX ? sB[CW * LDB + (t * 16 + ln) * LDB + kk + lq] : 0.0;
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            if (wave + i * NW < ntiles) {
+              acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, acc_r[i][t], 0, 0, 0);
+              if (CPLX) {
+                acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, acc_r[i][t], 0, 0, 0);
+                acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, acc_i[i][t], 0, 0, 0);
+                acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, acc_i[i][t], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // epilogue: propagator of the next gap, per-column max, rescale, store
+    const double* e2 = I.esh + I.eoff[s2];
+    double cm[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      cm[t] = 0.0;
+      const double dt = s_dt[t * 16 + ln];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = wave + i * NW;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * q + lq;
+            const double p = (m < d_out) ? exp(-dt * e2[m]) : 0.0;
+            acc_r[i][t][q] *= p;
+            cm[t] = fmax(cm[t], fabs(acc_r[i][t][q]));
+            if (CPLX) {
+              acc_i[i][t][q] *= p;
+              cm[t] = fmax(cm[t], fabs(acc_i[i][t][q]));
+            }
+          }
+        }
+      }
+      cm[t] = fmax(cm[t], __shfl_xor(cm[t], 16));
+      cm[t] = fmax(cm[t], __shfl_xor(cm[t], 32));
+      if (lq == 0) s_cmax[wave * CW + t * 16 + ln] = cm[t];
+    }
+    __syncthreads();
+    if (tid < CW) {
+      double M = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) M = fmax(M, s_cmax[w2 * CW + tid]);
+      int e = 0;
+      if (M > 0.0) frexp(M, &e);
+      s_e[tid] = e;
+      if (s_gcol[tid] >= 0) G.colexp[s_gcol[tid]] += e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int j = t * 16 + ln;
+      const long long g = s_gcol[j];
+      if (g < 0) continue;
+      const double sc = ldexp(1.0, -s_e[j]);
+      double* col = Xout + g * XR;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = wave + i * NW;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * q + lq;
+            col[m] = acc_r[i][t][q] * sc;
+            if (CPLX) col[plane + m] = acc_i[i][t][q] * sc;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// combine
+// ---------------------------------------------------------------------------
+// One wavefront per configuration: lanes over the columns of each string.
+__global__ __launch_bounds__(256) void k_gcombine(DevImp I, BatchArgs B, GroupArgs G) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= B.n_cfg) return;
+  ctr_value v;
+  v.re = v.im = v.log_scale = 0.0;
+  const int flags = B.cfg_flags[c];
+  v.flags = flags;
+  v.n_strings = B.cfg_nstr[c];
+  v.log_bound = B.cfg_logB[c];
+  if (!(flags & (CTR_FLAG_INVALID | CTR_FLAG_REJECTED | CTR_FLAG_ZERO))) {
+    const double ln2 = 0.69314718055994530942;
+    const StrRec* recs = B.rec + (long long)c * I.n_sec;
+    double lmax = -INFINITY;
+    for (int q = 0; q < I.n_sec; ++q) {
+      const StrRec R = recs[q];
+      if (R.n_panels == 0) continue;
+      const long long cb = G.s_colbase[B.cfg_off[c] + R.loc_off];
+      for (int j = lane; j < R.width; j += 64) {
+        const PanelRes P = G.colres[cb + j];
+        if (P.re != 0.0 || P.im != 0.0) lmax = fmax(lmax, P.e2 * ln2 - R.L);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+    if (lmax > -INFINITY) {
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q < I.n_sec; ++q) {
+        const StrRec R = recs[q];
+        if (R.n_panels == 0) continue;
+        const long long cb = G.s_colbase[B.cfg_off[c] + R.loc_off];
+        for (int j = lane; j < R.width; j += 64) {
+          const PanelRes P = G.colres[cb + j];
+          if (P.re != 0.0 || P.im != 0.0) {
+            const double f = exp(P.e2 * ln2 - R.L - lmax);
+            sr += P.re * f;
+            si += P.im * f;
+          }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
+      }
+      v.re = sr;
+      v.im = si;
+      v.log_scale = lmax - I.beta * I.E0;
+    }
+  }
+  if (lane == 0) B.out[c] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GVariant {
+  const void* fn;
+  int nw, cw;
+};
+
+template <bool CPLX, int NW, int RT, int CT>
+GVariant make_gvariant() {
+  return GVariant{reinterpret_cast<const void*>(&k_gstep<CPLX, NW, RT, CT>), NW, CT * 16};
+}
+
+bool pick_gvariant(const DevImp& imp, GVariant* v) {
+  const int tiles = imp.xrows / 16;
+  if (imp.is_complex) {
+    if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
+    else if (tiles <= 24) *v = make_gvariant<true, 8, 3, 2>();
+    else return false;
+  } else {
+    if (tiles <= 8) *v = make_gvariant<false, 4, 2, 4>();
+    else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
+    else return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+int group_grid(const DevImp& imp, int device, int* cw_step) {
+  GVariant v;
+  if (!pick_gvariant(imp, &v)) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.nw * 64, 0) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (cw_step) *cw_step = v.cw;
+  return per_cu > 0 ? per_cu * cus : 0;
+}
+
+hipError_t launch_group_prepare(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, long long max_strings,
+                                hipStream_t stream) {
+  if (max_strings > 0)
+    hipLaunchKernelGGL(k_gstrings, dim3((unsigned)((max_strings + 255) / 256)), dim3(256), 0, stream, imp, b, g);
+  hipLaunchKernelGGL(k_gscan1, dim3(1), dim3(1024), 0, stream, imp, b, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream) {
+  const unsigned sb = (unsigned)((g.S + 255) / 256);
+  if (g.S > 0) hipLaunchKernelGGL(k_gwalk, dim3(sb), dim3(256), 0, stream, imp, b, g, 0);
+  if (g.R > 1) hipLaunchKernelGGL(k_gsched, dim3(g.R - 1), dim3(1024), 0, stream, imp, g);
+  if (g.S > 0) hipLaunchKernelGGL(k_gwalk, dim3(sb), dim3(256), 0, stream, imp, b, g, 1);
+  if (g.R > 1) {
+    hipLaunchKernelGGL(k_gcolpref, dim3(g.R - 1), dim3(1024), 0, stream, imp, b, g);
+    hipLaunchKernelGGL(k_gscan2, dim3(1), dim3(1024), 0, stream, g);
+    const long long nk = (long long)(g.R - 1) * 2 * imp.n_sec * imp.nops;
+    hipLaunchKernelGGL(k_gkeys, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, stream, imp, g);
+    const long long ns = (long long)(g.R - 1) * g.S;
+    if (ns > 0) hipLaunchKernelGGL(k_gitems, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, stream, imp, b, g);
+  }
+  if (g.S > 0) {
+    if (imp.is_complex)
+      hipLaunchKernelGGL(k_gfirst<true>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
+    else
+      hipLaunchKernelGGL(k_gfirst<false>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
+                              hipStream_t stream) {
+  GVariant v;
+  if (!pick_gvariant(imp, &v) || grid <= 0) return hipErrorInvalidValue;
+  void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b), const_cast<GroupArgs*>(&g), &r};
+  return hipLaunchKernel(v.fn, dim3(grid), dim3(v.nw * 64), args, 0, stream);
+}
+
+hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream) {
+  if (b.n_cfg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gcombine, dim3((b.n_cfg + 3) / 4), dim3(256), 0, stream, imp, b, g);
+  return hipGetLastError();
+}
+
+}  // namespace ctr

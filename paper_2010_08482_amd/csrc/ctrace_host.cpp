@@ -34,6 +34,8 @@ struct ctr_ctx {
   int grid_split = 0;
   int grid_wave = 0;  // wavefront-per-panel kernel (panels of 8 columns), 0 = not applicable
   int grid_big = 0;   // streaming kernel
+  int grid_group = 0;  // block-grouped rounds, 0 = not applicable
+  int cw_group = 0;    // columns per grouped work item
   double* xbuf = nullptr;  // the streaming kernel's per-workgroup X buffers
   unsigned int* counter = nullptr;
   bool timing = false;
@@ -113,9 +115,100 @@ bool carve(ctr_ctx* ctx, Bump& b, int n_cfg, BatchArgs& a) {
          a.cfg_bsum && a.cfg_rej;
 }
 
-enum class Kernel { Wave, Block, Stream };
+enum class Kernel { Wave, Block, Stream, Group };
 
-ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kernel kind) {
+// Smallest batch for which AUTO takes the block-grouped rounds: below it the
+// per-round launches cost more than the shared block reads save.
+constexpr int kGroupMinBatch = 256;
+
+// Block-grouped rounds for the configurations of `a` (scratch after `b`'s
+// offset).  Returns CTR_ERR_OOM, with nothing enqueued past the plan, if the
+// carried matrices of the surviving strings do not fit the arena.
+ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b) {
+  a.panel = ctr::kGroupPanel;
+  hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
+  if ((e = ctr::launch_scan(a, ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "scan kernel");
+  ctr::GroupArgs g{};
+  const long long max_s = (long long)a.n_cfg * ctx->n_sec;
+  g.s_cfg = (int*)b.take((size_t)max_s * sizeof(int));
+  g.s_rec = (int*)b.take((size_t)max_s * sizeof(int));
+  g.s_width = (int*)b.take((size_t)max_s * sizeof(int));
+  g.s_n = (int*)b.take((size_t)max_s * sizeof(int));
+  g.s_colbase = (long long*)b.take((size_t)max_s * sizeof(long long));
+  g.info = (long long*)b.take(8 * sizeof(long long));
+  if (!g.s_cfg || !g.s_rec || !g.s_width || !g.s_n || !g.s_colbase || !g.info)
+    return fail(ctx, CTR_ERR_OOM, "arena too small");
+  g.cw_step = ctx->cw_group;
+  g.cw_close = ctr::kGroupCloseCols;
+  if ((e = ctr::launch_group_prepare(ctx->imp, a, g, max_s, ctx->stream)) != hipSuccess)
+    return hip_fail(ctx, e, "grouped prepare kernels");
+  long long info[5] = {0, 0, 0, 0, 0};
+  HIP_TRY(ctx, hipMemcpyAsync(info, g.info, sizeof(info), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  g.S = info[0];
+  g.T = info[1];
+  g.R = (int)info[2];
+  g.CS = info[3];
+  g.NI = info[4];
+  if (g.T >= (1LL << 31) || g.S >= (1LL << 31)) return fail(ctx, CTR_ERR_OOM, "batch too large for one chunk");
+  const long long NK = 2LL * ctx->n_sec * ctx->nops;
+  const long long R = std::max(g.R, 1);
+  const int planes = ctx->imp.is_complex ? 2 : 1;
+  const size_t xdoubles = (size_t)std::max(g.T, 1LL) * ctx->imp.xrows * planes;
+  g.hist = (int*)b.take((size_t)(R * NK) * sizeof(int));
+  g.hcols = (int*)b.take((size_t)(R * NK) * sizeof(int));
+  g.cursor = (int*)b.take((size_t)(R * NK) * sizeof(int));
+  g.gstart = (int*)b.take((size_t)(R * (NK + 1)) * sizeof(int));
+  g.istart = (int*)b.take((size_t)(R * (NK + 1)) * sizeof(int));
+  g.n_items = (int*)b.take((size_t)R * sizeof(int));
+  g.counters = (unsigned int*)b.take((size_t)R * sizeof(unsigned int));
+  g.sorted = (int*)b.take((size_t)(R * std::max(g.S, 1LL)) * sizeof(int));
+  g.colpref = (int*)b.take((size_t)(R * std::max(g.S, 1LL)) * sizeof(int));
+  g.X[0] = (double*)b.take(xdoubles * sizeof(double));
+  g.X[1] = (double*)b.take(xdoubles * sizeof(double));
+  g.colexp = (int*)b.take((size_t)std::max(g.T, 1LL) * sizeof(int));
+  g.colres = (PanelRes*)b.take((size_t)std::max(g.T, 1LL) * sizeof(PanelRes));
+  g.rcols = (long long*)b.take((size_t)R * sizeof(long long));
+  g.rcoloff = (long long*)b.take((size_t)R * sizeof(long long));
+  g.ritemoff = (long long*)b.take((size_t)R * sizeof(long long));
+  g.item_key = (int*)b.take((size_t)std::max(g.NI, 1LL) * sizeof(int));
+  g.colg = (int*)b.take((size_t)std::max(g.CS, 1LL) * sizeof(int));
+  g.colaux = (double*)b.take((size_t)std::max(g.CS, 1LL) * sizeof(double));
+  if (!g.hist || !g.hcols || !g.cursor || !g.gstart || !g.istart || !g.n_items || !g.counters || !g.sorted ||
+      !g.colpref || !g.X[0] || !g.X[1] || !g.colexp || !g.colres || !g.rcols || !g.rcoloff || !g.ritemoff ||
+      !g.item_key || !g.colg || !g.colaux)
+    return fail(ctx, CTR_ERR_OOM, "arena too small for the grouped rounds");
+  HIP_TRY(ctx, hipMemsetAsync(g.rcols, 0, (size_t)R * sizeof(long long), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.n_items, 0, (size_t)R * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.hist, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.hcols, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.cursor, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.counters, 0, (size_t)R * sizeof(unsigned int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.colres, 0, (size_t)std::max(g.T, 1LL) * sizeof(PanelRes), ctx->stream));
+  if ((e = ctr::launch_group_schedule(ctx->imp, a, g, ctx->stream)) != hipSuccess)
+    return hip_fail(ctx, e, "grouped schedule kernels");
+  for (int r = 1; r < g.R; ++r) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (ctx->timing) {
+      HIP_TRY(ctx, hipEventCreate(&t0));
+      HIP_TRY(ctx, hipEventCreate(&t1));
+      HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
+    }
+    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, ctx->grid_group, ctx->stream)) != hipSuccess)
+      return hip_fail(ctx, e, "grouped round kernel");
+    if (ctx->timing) {
+      HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
+      ctx->events.emplace_back(t0, t1);
+    }
+  }
+  if ((e = ctr::launch_group_combine(ctx->imp, a, g, ctx->stream)) != hipSuccess)
+    return hip_fail(ctx, e, "grouped combine kernel");
+  return CTR_OK;
+}
+
+ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kernel kind, Bump* b) {
+  if (kind == Kernel::Group && !plan_only) return enqueue_grouped(ctx, a, *b);
   a.panel = kind == Kernel::Wave ? ctr::kWavePanelHost : ctr::kPanel;
   hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
@@ -134,6 +227,7 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
       e = ctr::launch_chain(ctx->imp, a, split, split ? ctx->grid_split : ctx->grid, ctx->stream);
       break;
     case Kernel::Stream: e = ctr::launch_chain_big(ctx->imp, a, ctx->xbuf, ctx->grid_big, ctx->stream); break;
+    case Kernel::Group: e = hipErrorInvalidValue; break;  // handled by enqueue_grouped
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "chain kernel");
   if (ctx->timing) {
@@ -153,7 +247,8 @@ ctr_status ready(ctr_ctx* ctx) {
   return CTR_OK;
 }
 
-ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* kind) {
+ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* kind, long long n_cfg = 1,
+                      bool lazy = false) {
   *split = false;
   int want = CTR_KERNEL_AUTO;
   if (opts) {
@@ -166,14 +261,16 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       return fail(ctx, CTR_ERR_ARG, "unknown precision");
     }
     want = opts->kernel;
-    if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_STREAM) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
+    if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_GROUPED) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
   }
+  const bool group_ok = !*split && !lazy && ctx->grid_group > 0;
   const bool wave_ok = !*split && ctx->grid_wave > 0;
   const bool block_ok = (*split ? ctx->grid_split : ctx->grid) > 0;
   const bool stream_ok = !*split && ctx->grid_big > 0;
   switch (want) {
     case CTR_KERNEL_AUTO:
-      if (wave_ok) *kind = Kernel::Wave;
+      if (group_ok && n_cfg >= kGroupMinBatch) *kind = Kernel::Group;
+      else if (wave_ok) *kind = Kernel::Wave;
       else if (block_ok) *kind = Kernel::Block;
       else if (stream_ok) *kind = Kernel::Stream;
       else return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel can run this impurity in this precision");
@@ -186,18 +283,30 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       if (!block_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "the panel of the largest sector does not fit LDS");
       *kind = Kernel::Block;
       return CTR_OK;
-    default:
+    case CTR_KERNEL_STREAM:
       if (!stream_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "streaming kernel runs FP64 only");
       *kind = Kernel::Stream;
       return CTR_OK;
+    default:
+      if (!group_ok)
+        return fail(ctx, CTR_ERR_UNSUPPORTED, "grouped rounds need FP64, no lazy threshold and sectors <= 384 states");
+      *kind = Kernel::Group;
+      return CTR_OK;
   }
+}
+
+// The kernel AUTO takes when the grouped rounds do not fit the arena.
+Kernel per_string_kernel(const ctr_ctx* ctx) {
+  if (ctx->grid_wave > 0) return Kernel::Wave;
+  if (ctx->grid > 0) return Kernel::Block;
+  return Kernel::Stream;
 }
 
 // Host-pointer batch: validates, then runs arena-sized chunks; `mode` 0 =
 // traces, 1 = bounds only (out_bound), thresholds optional.
 ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
                       const double* log_thr, ctr_value* out, double* out_bound, int mode, bool split,
-                      Kernel kind, BatchArgs* last = nullptr) {
+                      Kernel kind, BatchArgs* last = nullptr, bool auto_kind = false) {
   if (n_cfg < 0 || (n_cfg > 0 && (!offsets || (!out && !out_bound))))
     return fail(ctx, CTR_ERR_ARG, "null argument");
   if (n_cfg == 0) return CTR_OK;
@@ -210,13 +319,14 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
   }
   const size_t per_cfg = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64;
   int32_t c0 = 0;
+  int32_t cap = n_cfg;  // chunk cap, halved while the grouped rounds do not fit
   std::vector<long long> offs;
   while (c0 < n_cfg) {
     // largest chunk that fits the free arena
     const size_t free_bytes = ctx->arena_bytes - ctx->resident;
     int32_t c1 = c0;
     size_t need = 8 * kAlign;
-    while (c1 < n_cfg) {
+    while (c1 < n_cfg && c1 - c0 < cap) {
       const size_t more = per_cfg + (size_t)(offsets[c1 + 1] - offsets[c1]) * (sizeof(double) + sizeof(int32_t));
       if (need + more > free_bytes) break;
       need += more;
@@ -247,7 +357,20 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     a.op = d_op;
     a.log_thr = d_thr;
     a.out = d_out;
-    ctr_status s = enqueue(ctx, a, mode == 1, split, kind);
+    ctr_status s = enqueue(ctx, a, mode == 1, split, kind, &b);
+    if (s == CTR_ERR_OOM && kind == Kernel::Group) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (m > 1) {
+        cap = m / 2;
+      } else if (auto_kind) {
+        kind = per_string_kernel(ctx);
+        cap = n_cfg;
+      } else {
+        return s;
+      }
+      ctx->err.clear();
+      continue;
+    }
     if (s != CTR_OK) return s;
     if (mode == 1) {
       HIP_TRY(ctx, hipMemcpyAsync(out_bound + c0, a.cfg_logB, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -512,6 +635,8 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, true, nullptr);
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
+  ctx->cw_group = 0;
+  ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, &ctx->cw_group);
   ctx->xbuf = nullptr;
   if (ctx->grid_big > 0) {
     ctx->xbuf = (double*)b.take(ctr::big_xbuf_doubles(ctx->imp, ctx->grid_big) * sizeof(double));
@@ -530,8 +655,9 @@ ctr_status ctr_trace_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, 
   if (s != CTR_OK) return s;
   bool split = false;
   Kernel kind = Kernel::Block;
-  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
-  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind);
+  if ((s = check_opts(ctx, opts, &split, &kind, n_cfg)) != CTR_OK) return s;
+  const bool auto_kind = !opts || opts->kernel == CTR_KERNEL_AUTO;
+  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind, nullptr, auto_kind);
 }
 
 ctr_status ctr_trace(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, const ctr_opts* opts,
@@ -548,7 +674,7 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offs
   if (s != CTR_OK) return s;
   bool split = false;
   Kernel kind = Kernel::Block;
-  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
+  if ((s = check_opts(ctx, opts, &split, &kind, n_cfg, true)) != CTR_OK) return s;
   if (n_cfg > 0 && !log_threshold) return fail(ctx, CTR_ERR_ARG, "null log_threshold");
   return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split, kind);
 }
@@ -592,14 +718,16 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
   if (s != CTR_OK) return s;
   bool split = false;
   Kernel kind = Kernel::Block;
-  if ((s = check_opts(ctx, opts, &split, &kind)) != CTR_OK) return s;
+  if ((s = check_opts(ctx, opts, &split, &kind, n_cfg)) != CTR_OK) return s;
+  const bool auto_kind = !opts || opts->kernel == CTR_KERNEL_AUTO;
   if (n_cfg < 0 || (n_cfg > 0 && (!d_offsets || !d_out))) return fail(ctx, CTR_ERR_ARG, "null argument");
   const size_t free_bytes = ctx->arena_bytes - ctx->resident;
   const size_t per_cfg = scratch_per_cfg(ctx) + 64;
   const long long fit = (long long)((free_bytes > 8 * kAlign ? free_bytes - 8 * kAlign : 0) / per_cfg);
   if (n_cfg > 0 && fit < 1) return fail(ctx, CTR_ERR_OOM, "arena too small for one configuration");
+  long long cap = fit;  // chunk cap, halved while the grouped rounds do not fit
   for (int32_t c0 = 0; c0 < n_cfg;) {
-    const int32_t m = (int32_t)std::min<long long>(fit, n_cfg - c0);
+    const int32_t m = (int32_t)std::min<long long>(cap, n_cfg - c0);
     Bump b{ctx->arena, ctx->resident, ctx->arena_bytes};
     BatchArgs a{};
     if (!carve(ctx, b, m, a)) return fail(ctx, CTR_ERR_OOM, "arena too small");
@@ -608,7 +736,21 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
     a.op = d_op;
     a.log_thr = nullptr;
     a.out = d_out + c0;
-    if ((s = enqueue(ctx, a, false, split, kind)) != CTR_OK) return s;
+    s = enqueue(ctx, a, false, split, kind, &b);
+    if (s == CTR_ERR_OOM && kind == Kernel::Group) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (m > 1) {
+        cap = m / 2;
+      } else if (auto_kind) {
+        kind = per_string_kernel(ctx);
+        cap = fit;
+      } else {
+        return s;
+      }
+      ctx->err.clear();
+      continue;
+    }
+    if (s != CTR_OK) return s;
     c0 += m;
   }
   return CTR_OK;

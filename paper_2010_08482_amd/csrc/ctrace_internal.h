@@ -90,7 +90,46 @@ struct BatchArgs {
   int* cfg_rej;                      // [n_cfg] 1 once the bound sum fell below the threshold
 };
 
-// Launchers (ctrace_kernels.hip).  All enqueue on `stream`.
+// Block-grouped evaluation (ctrace_group.hip): every surviving string is one
+// chain over its start sector's columns; all strings advance one operator per
+// round and the strings at the same block in a round share one wide product.
+// Round r >= 1, group key k: block q*nops+op (k < NB) or, at a string's last
+// operator, NB + block (the close); NB = n_sec * nops, NK = 2 * NB.
+struct GroupArgs {
+  long long S;                 // surviving strings of the batch
+  long long T;                 // columns (sum of string widths)
+  int R;                       // rounds (largest operator count)
+  int cw_step, cw_close;       // columns per work item (products, closes)
+  long long CS;                // column-steps: sum over strings of width * (operators - 1)
+  long long NI;                // bound on the work items of all rounds
+  int* s_cfg;                  // [S] configuration of the string
+  int* s_rec;                  // [S] its record (start-sector index) in the configuration
+  int* s_width;                // [S] columns of the string
+  int* s_n;                    // [S] operators of its configuration
+  long long* s_colbase;        // [S] first column of the string
+  long long* info;             // [5] S, T, R, CS, NI (device copy, read back by the host)
+  int* hist;                   // [R][NK] strings per group
+  int* hcols;                  // [R][NK] columns per group
+  int* cursor;                 // [R][NK] scatter cursors
+  int* gstart;                 // [R][NK+1] first position of every group in `sorted`
+  int* istart;                 // [R][NK+1] first work item of every group
+  int* n_items;                // [R]
+  unsigned int* counters;      // [R] persistent-kernel work counters
+  int* sorted;                 // [R][S] strings in group order
+  int* colpref;                // [R][S] first column (round-relative) of every sorted string
+  long long* rcols;            // [R] columns of round r
+  long long* rcoloff;          // [R] first column-step of round r in colg / colaux
+  long long* ritemoff;         // [R] first work item of round r in item_key
+  int* item_key;               // [NI] group of every work item
+  int* colg;                   // [CS] column-steps in group order: global column
+  double* colaux;              // [CS] gap in front of the next operator (products) or the
+                               //      column's index inside its start sector (closes)
+  double* X[2];                // carried matrices, ping-pong: column g at g * xrows (imaginary plane at + T * xrows)
+  int* colexp;                 // [T] accumulated power of two of every column
+  PanelRes* colres;            // [T] closed column values
+};
+
+// Launchers (ctrace_kernels.hip, ctrace_group.hip).  All enqueue on `stream`.
 hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
 hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream);
@@ -107,5 +146,15 @@ constexpr int kWavePanelHost = 8;
 int big_grid(const DevImp& imp, int device, size_t* lds_bytes);
 size_t big_xbuf_doubles(const DevImp& imp, int grid);
 hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf, int grid, hipStream_t stream);
+// Block-grouped path (sectors of at most 384 states); grid 0 = not applicable.
+int group_grid(const DevImp& imp, int device, int* cw_step);
+hipError_t launch_group_prepare(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, long long max_strings,
+                                hipStream_t stream);
+hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
+                              hipStream_t stream);
+hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+constexpr int kGroupCloseCols = 64;
+constexpr int kGroupPanel = 1 << 24;  // plan panel width in grouped mode: one panel per string
 
 }  // namespace ctr

@@ -27,6 +27,7 @@ CTR_KERNEL_AUTO = 0
 CTR_KERNEL_WAVE = 1
 CTR_KERNEL_BLOCK = 2
 CTR_KERNEL_STREAM = 3
+CTR_KERNEL_GROUPED = 4
 
 
 class ctr_value(ctypes.Structure):
@@ -264,7 +265,7 @@ def value_pair(v):
 class TraceContext:
     """A ctrace context with its arena and stream taken from PyTorch."""
 
-    def __init__(self, table, arena_bytes: int | None = None, device: int = 0):
+    def __init__(self, table, arena_bytes: int | None = None, device: int = 0, scratch_bytes: int = 1 << 30):
         import torch
 
         if not torch.cuda.is_available():
@@ -272,14 +273,16 @@ class TraceContext:
         self.device = int(device)
         self.table = table
         if arena_bytes is None:
-            arena_bytes = self.default_arena_bytes(table)
+            arena_bytes = self.default_arena_bytes(table, scratch_bytes)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = ctr_create(self.device, self.arena.data_ptr(), self.arena.numel(), self.stream.cuda_stream)
         ctr_set_impurity(self.ctx, table)
 
     @staticmethod
-    def default_arena_bytes(table) -> int:
+    def default_arena_bytes(table, scratch_bytes: int = 1 << 30) -> int:
+        """Operator blocks and kernel buffers of `table` plus `scratch_bytes` of
+        per-call scratch (batches larger than the scratch run in chunks)."""
         es = 16 if table.is_complex else 8
         blocks = 0
         d = np.asarray(table.dims)
@@ -290,7 +293,7 @@ class TraceContext:
                     blocks += ((int(d[t]) + 15) // 16 * 16) * ((int(d[q]) + 3) // 4 * 4) * es + 256
         xr = (int(d.max()) + 15) // 16 * 16
         stream_buffers = 2 * (2 if table.is_complex else 1) * xr * 16 * 8 * 1024
-        return int(blocks + stream_buffers + (256 << 20))
+        return int(blocks + stream_buffers + scratch_bytes)
 
     def close(self):
         if getattr(self, "ctx", None):

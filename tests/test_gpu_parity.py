@@ -305,10 +305,48 @@ def test_arena_oom_then_chunked_batches_identical(lib, ctx):
     assert e.value.status == -2
     small = lib.TraceContext(tab, arena_bytes=resident + (1 << 20))
     try:
-        out = small.trace_batch(cfgs)  # ~5 KiB of scratch per configuration: several chunks
-        assert np.array_equal(out["re"], ref["re"]) and np.array_equal(out["log_scale"], ref["log_scale"])
+        # ~5 KiB of scratch per configuration: several chunks of the wavefront kernel
+        ref_w = big.trace_batch(cfgs, kernel=lib.CTR_KERNEL_WAVE)
+        out = small.trace_batch(cfgs, kernel=lib.CTR_KERNEL_WAVE)
+        assert np.array_equal(out["re"], ref_w["re"]) and np.array_equal(out["log_scale"], ref_w["log_scale"])
+        # grouped rounds: the carried matrices do not fit, the batch is halved until they do;
+        # every column's arithmetic is independent of how the batch is grouped
+        mid = lib.TraceContext(tab, arena_bytes=resident + (8 << 20))
+        try:
+            out = mid.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+            ref_g = big.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+            assert np.array_equal(out["re"], ref_g["re"]) and np.array_equal(out["log_scale"], ref_g["log_scale"])
+            assert np.array_equal(ref["re"], ref_g["re"])  # the automatic choice for 300 traces is grouped
+            # AUTO falls back to the per-string kernel when even one configuration does not fit
+            out = small.trace_batch(cfgs)
+            assert np.array_equal(out["re"], ref_w["re"])
+        finally:
+            mid.close()
     finally:
         small.close()
+
+
+def test_grouped_rounds_agree_with_per_string_kernels(lib, ctx):
+    """Block-grouped rounds against the wavefront kernel on 2000 d-shell traces
+    (different MFMA shapes: rounding-level agreement) and against the LDS
+    workgroup kernel on the complex 327-state f-shell."""
+    tab, c = ctx("dshell")
+    cfgs = make_configs(1, 2000)
+    say("[gpu] grouped vs wavefront dshell x2000")
+    a = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+    b = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_WAVE)
+    assert np.array_equal(a["flags"], b["flags"]) and np.array_equal(a["n_strings"], b["n_strings"])
+    worst = max((rel_err(pair(x), pair(y)) for x, y in zip(a, b) if y["re"] != 0), default=0.0)
+    say(f"grouped vs wavefront worst rel {worst:.2e}")
+    assert worst < 1e-11
+    tab, c = ctx("fshell")
+    cfgs = make_configs(2, 300)
+    say("[gpu] grouped vs block fshell x300")
+    a = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+    b = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_BLOCK)
+    worst = max((rel_err(pair(x), pair(y)) for x, y in zip(a, b) if y["re"] != 0 or y["im"] != 0), default=0.0)
+    say(f"grouped vs block fshell worst rel {worst:.2e}")
+    assert worst < 1e-9
 
 
 def test_determinism_and_batch_order(ctx):
@@ -328,7 +366,9 @@ def test_lazy_bound_and_rejection(lib, ctx):
     cfgs = make_configs(1, 300)
     offs, tau, op = pack(cfgs)
     say("[gpu] lazy bounds dshell x300")
-    exact = c.trace_packed(offs, tau, op)
+    # reference through the same kernel the lazy call runs (nothing rejected at -inf)
+    exact = c.lazy_batch(offs, tau, op, np.full(len(cfgs), -np.inf))
+    assert not np.any(exact["flags"] & 2)
     la = np.array([lib.log_abs(v) for v in exact])
     lb = exact["log_bound"]
     assert np.all(la <= lb + 1e-9)
@@ -364,7 +404,8 @@ def test_lazy_refinement_rejects_only_below_threshold(lib, ctx, name, cid, count
          for i in range(count)]
     offs, tau, op = pack(strings)
     say(f"[gpu] lazy refinement {name} x{count} kernel={kernel} split={split}")
-    exact = c.trace_packed(offs, tau, op, prec, k)
+    exact = c.lazy_batch(offs, tau, op, np.full(len(strings), -np.inf), prec, k)
+    assert not np.any(exact["flags"] & 2)
     la = np.array([lib.log_abs(v) for v in exact])
     lb = exact["log_bound"]
     live = np.isfinite(la)
@@ -380,11 +421,12 @@ def test_lazy_refinement_rejects_only_below_threshold(lib, ctx, name, cid, count
     say(f"lazy refinement {name}: {int(np.sum(rej))} of {int(np.sum(thr > la))} rejectable configurations rejected")
 
 
-@pytest.mark.parametrize("kernel", ["wave", "block", "stream"])
+@pytest.mark.parametrize("kernel", ["wave", "block", "stream", "grouped"])
 def test_every_chain_kernel_matches_the_oracle(lib, ctx, kernel):
-    """The three chain kernels (wavefront, LDS workgroup, streaming) forced on
-    impurities the oracle covers."""
-    k = {"wave": lib.CTR_KERNEL_WAVE, "block": lib.CTR_KERNEL_BLOCK, "stream": lib.CTR_KERNEL_STREAM}[kernel]
+    """The chain kernels (wavefront, LDS workgroup, streaming, block-grouped
+    rounds) forced on impurities the oracle covers."""
+    k = {"wave": lib.CTR_KERNEL_WAVE, "block": lib.CTR_KERNEL_BLOCK, "stream": lib.CTR_KERNEL_STREAM,
+         "grouped": lib.CTR_KERNEL_GROUPED}[kernel]
     g = load_golden("dshell_config1")
     tab, c = ctx("dshell")
     recs = g["records"][:96]
@@ -410,6 +452,13 @@ def test_kernel_option_errors(lib, ctx):
         c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_STREAM)
     assert e.value.status == -7
     with pytest.raises(lib.CtraceError) as e:
+        c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED)
+    assert e.value.status == -7
+    offs, tau, op = pack(make_configs(1, 4))
+    with pytest.raises(lib.CtraceError) as e:
+        c.lazy_batch(offs, tau, op, np.zeros(4), kernel=lib.CTR_KERNEL_GROUPED)
+    assert e.value.status == -7
+    with pytest.raises(lib.CtraceError) as e:
         c.trace([0.5, 1.0], [1, 0], kernel=7)
     assert e.value.status == -1
 
@@ -432,6 +481,9 @@ def test_sectors_of_3432_states_density_density_vs_enumeration(lib, ctx, phase_s
     assert sum(1 for r in refs if r[0] != 0) >= 5
     with pytest.raises(lib.CtraceError) as e:
         c.trace(cfgs[0].tau, cfgs[0].op, kernel=lib.CTR_KERNEL_BLOCK)
+    assert e.value.status == -7
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace(cfgs[0].tau, cfgs[0].op, kernel=lib.CTR_KERNEL_GROUPED)
     assert e.value.status == -7
 
 
