@@ -71,15 +71,15 @@ def algorithmic_flops(tab, strings):
 
 def chain_kernel_name(tab, n_cfg):
     """Kernel the library's automatic choice runs for a batch of FP64 traces of
-    this table: block-grouped rounds for batches of at least 256 traces with
-    sectors of at most 384 states, else the wavefront kernel for sectors of at
-    most 128 states, the LDS workgroup kernel while a 16-column panel fits LDS,
-    the streaming kernel beyond."""
+    this table: the wavefront kernel for sectors of at most 128 states, else
+    block-grouped rounds for batches of at least 256 traces with sectors of at
+    most 384 states, else the LDS workgroup kernel while a 16-column panel fits
+    LDS, the streaming kernel beyond."""
     xr = (tab.max_dim + 15) // 16 * 16
-    if n_cfg >= 256 and xr <= 384:
-        return "k_gstep"
     if xr <= 128:
         return "k_chain_wave"
+    if n_cfg >= 256 and xr <= 384:
+        return "k_gstep"
     if xr <= (576 if tab.is_complex else 1024):
         return "k_chain"
     return "k_chain_big"

@@ -28,6 +28,8 @@
 //               with the propagator of the next gap and the per-column
 //               power-of-two rescale fused into the epilogue; strings at
 //               their last operator only form the diagonal of F * X
+//   k_gstep_wave  the same for sectors of at most 128 (real) or 32 (complex)
+//               states: one wavefront per 16-column item, no barriers
 //   k_gcombine  one wavefront per configuration: (mantissa, exponent) merge
 //               of all columns of all its strings
 #include <math.h>
@@ -390,15 +392,18 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
   const long long plane = G.T * (long long)XR;
   const double* Xin = G.X[(r + 1) & 1];
   double* Xout = G.X[r & 1];
-  const int n_items = G.n_items[r];
   const int* istart = G.istart + (long long)r * (NK + 1);
   const int* gstart = G.gstart + (long long)r * (NK + 1);
   const int* hcols = G.hcols + (long long)r * NK;
   const int* colpref = G.colpref + (long long)r * G.S;
 
   const long long* ritemoff = G.ritemoff;
+  // item i is served by counter i % kGroupCounters
+  const int n_items = G.n_items[r];
+  const int slot = blockIdx.x % kGroupCounters;
+  unsigned int* counter = G.counters + ((long long)r * kGroupCounters + slot) * 32;
   for (;;) {
-    if (tid == 0) s_item = (int)atomicAdd(G.counters + r, 1u);
+    if (tid == 0) s_item = slot + kGroupCounters * (int)atomicAdd(counter, 1u);
     __syncthreads();
     const int item = s_item;
     if (item >= n_items) break;
@@ -589,6 +594,182 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
   }
 }
 
+// Sectors of at most 16 * MT states: one wavefront per work item of 16
+// columns of one group, all row tiles in registers, no workgroup barrier.
+// Lane l supplies A[row l%16][k l/16] and B[k l/16][column l%16]; item q of
+// the 16x16x4 result is row 4q + l/16, column l%16, so the per-column max is
+// a reduction over the four lanes of a column (xor 16, 32).
+template <bool CPLX, int MT>
+__global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, GroupArgs G, int r) {
+  const int lane = threadIdx.x & 63;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  const int XR = I.xrows;
+  const long long plane = G.T * (long long)XR;
+  const double* Xin = G.X[(r + 1) & 1];
+  double* Xout = G.X[r & 1];
+  const int* istart = G.istart + (long long)r * (NK + 1);
+  const int* gstart = G.gstart + (long long)r * (NK + 1);
+  const int* hcols = G.hcols + (long long)r * NK;
+  const int* colpref = G.colpref + (long long)r * G.S;
+  const int* item_key = G.item_key + G.ritemoff[r];
+  const long long rcoloff = G.rcoloff[r];
+  typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+  // item i is served by counter i % kGroupCounters
+  const int n_items = G.n_items[r];
+  const int slot = (blockIdx.x * 4 + (threadIdx.x >> 6)) % kGroupCounters;
+  unsigned int* counter = G.counters + ((long long)r * kGroupCounters + slot) * 32;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = slot + kGroupCounters * (int)atomicAdd(counter, 1u);
+    item = __shfl(item, 0);
+    if (item >= n_items) break;
+    const int key = item_key[item];
+    const bool close = key >= NB;
+    const int blk = close ? key - NB : key;
+    const int cw = close ? G.cw_close : 16;
+    const int c0 = (item - istart[key]) * cw;
+    const int ncol = min(cw, hcols[key] - c0);
+    const long long relbase = rcoloff + colpref[gstart[key]] + c0;
+    const int s = blk / I.nops;
+    const int s2 = I.next[blk];
+    const int d_in = I.dim[s], d_out = I.dim[s2];
+    const int ld = (d_out + 15) & ~15;
+    const int kp = (d_in + 3) & ~3;
+    const double* Fr = I.pool + I.boff[blk];
+    const double* Fi = Fr + (long long)ld * kp;
+
+    if (close) {
+      for (int j = 0; j < ncol; ++j) {
+        const long long gcol = G.colg[relbase + j];
+        const int jj = (int)G.colaux[relbase + j];
+        const double* xr = Xin + gcol * XR;
+        double sr = 0.0, si = 0.0;
+        for (int k = lane; k < d_in; k += 64) {
+          const double fr = Fr[(long long)k * ld + jj], x = xr[k];
+          if (CPLX) {
+            const double fi = Fi[(long long)k * ld + jj], xi = xr[plane + k];
+            sr += fr * x - fi * xi;
+            si += fr * xi + fi * x;
+          } else {
+            sr += fr * x;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (lane == 0) {
+          PanelRes o;
+          o.re = sr;
+          o.im = si;
+          o.e2 = (double)G.colexp[gcol];
+          G.colres[gcol] = o;
+        }
+      }
+      continue;
+    }
+
+    const bool live = ln < ncol;
+    const long long gcol = live ? (long long)G.colg[relbase + ln] : 0;
+    const double dt = live ? G.colaux[relbase + ln] : 0.0;
+    const double* xr = Xin + gcol * XR;
+    const int ntiles = ld >> 4;
+    dbl4 acc_r[MT], acc_i[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      acc_r[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+      acc_i[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    // operands of the next k-step are loaded while the current one multiplies
+    double nar[MT], nai[MT], nbr, nbi;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      nar[t] = nai[t] = 0.0;
+      if (t < ntiles) {
+        nar[t] = Fr[(long long)lq * ld + t * 16 + ln];
+        if (CPLX) nai[t] = Fi[(long long)lq * ld + t * 16 + ln];
+      }
+    }
+    nbr = live ? xr[lq] : 0.0;
+    nbi = (CPLX && live) ? xr[plane + lq] : 0.0;
+    for (int k0 = 0; k0 < kp; k0 += 4) {
+      double ar[MT], ai[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        ar[t] = nar[t];
+        ai[t] = nai[t];
+      }
+      const double br = nbr, bi = nbi;
+      const int kn = k0 + 4;
+      if (kn < kp) {
+        const long long row = (long long)(kn + lq) * ld;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t < ntiles) {
+            nar[t] = Fr[row + t * 16 + ln];
+            if (CPLX) nai[t] = Fi[row + t * 16 + ln];
+          }
+        }
+        nbr = live ? xr[kn + lq] : 0.0;
+        nbi = (CPLX && live) ? xr[plane + kn + lq] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        if (t < ntiles) {
+          acc_r[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], br, acc_r[t], 0, 0, 0);
+          if (CPLX) {
+            acc_r[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[t], bi, acc_r[t], 0, 0, 0);
+            acc_i[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], bi, acc_i[t], 0, 0, 0);
+            acc_i[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[t], br, acc_i[t], 0, 0, 0);
+          }
+        }
+      }
+    }
+
+    // propagator of the next gap, per-column max, rescale, store
+    const double* e2 = I.esh + I.eoff[s2];
+    double cm = 0.0;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (t < ntiles) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = t * 16 + 4 * q + lq;
+          const double p = (m < d_out) ? exp(-dt * e2[m]) : 0.0;
+          acc_r[t][q] *= p;
+          cm = fmax(cm, fabs(acc_r[t][q]));
+          if (CPLX) {
+            acc_i[t][q] *= p;
+            cm = fmax(cm, fabs(acc_i[t][q]));
+          }
+        }
+      }
+    }
+    cm = fmax(cm, __shfl_xor(cm, 16));
+    cm = fmax(cm, __shfl_xor(cm, 32));
+    int e = 0;
+    if (cm > 0.0) frexp(cm, &e);
+    const double sc = ldexp(1.0, -e);
+    if (live) {
+      if (lq == 0) G.colexp[gcol] += e;
+      double* col = Xout + gcol * XR;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        if (t < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = t * 16 + 4 * q + lq;
+            col[m] = acc_r[t][q] * sc;
+            if (CPLX) col[plane + m] = acc_i[t][q] * sc;
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // combine
 // ---------------------------------------------------------------------------
@@ -659,14 +840,25 @@ GVariant make_gvariant() {
   return GVariant{reinterpret_cast<const void*>(&k_gstep<CPLX, NW, RT, CT>), NW, CT * 16};
 }
 
+template <bool CPLX, int MT>
+GVariant make_wvariant() {
+  return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT>), 4, 16};
+}
+
+// Small sectors: one wavefront per 16-column item (all row tiles in
+// registers); larger ones: a workgroup per 32/64-column item, rows split
+// over its wavefronts.
 bool pick_gvariant(const DevImp& imp, GVariant* v) {
   const int tiles = imp.xrows / 16;
   if (imp.is_complex) {
-    if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
+    if (tiles <= 2) *v = make_wvariant<true, 2>();
+    else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
     else if (tiles <= 24) *v = make_gvariant<true, 8, 3, 2>();
     else return false;
   } else {
-    if (tiles <= 8) *v = make_gvariant<false, 4, 2, 4>();
+    if (tiles <= 2) *v = make_wvariant<false, 2>();
+    else if (tiles <= 4) *v = make_wvariant<false, 4>();
+    else if (tiles <= 8) *v = make_wvariant<false, 8>();
     else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
     else return false;
   }
@@ -683,7 +875,8 @@ int group_grid(const DevImp& imp, int device, int* cw_step) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   if (cw_step) *cw_step = v.cw;
-  return per_cu > 0 ? per_cu * cus : 0;
+  const int grid = per_cu > 0 ? per_cu * cus : 0;
+  return grid >= kGroupCounters ? grid : 0;  // every counter needs at least one worker
 }
 
 hipError_t launch_group_prepare(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, long long max_strings,

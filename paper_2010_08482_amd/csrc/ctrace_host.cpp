@@ -162,7 +162,7 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b) {
   g.gstart = (int*)b.take((size_t)(R * (NK + 1)) * sizeof(int));
   g.istart = (int*)b.take((size_t)(R * (NK + 1)) * sizeof(int));
   g.n_items = (int*)b.take((size_t)R * sizeof(int));
-  g.counters = (unsigned int*)b.take((size_t)R * sizeof(unsigned int));
+  g.counters = (unsigned int*)b.take((size_t)R * ctr::kGroupCounters * 32 * sizeof(unsigned int));
   g.sorted = (int*)b.take((size_t)(R * std::max(g.S, 1LL)) * sizeof(int));
   g.colpref = (int*)b.take((size_t)(R * std::max(g.S, 1LL)) * sizeof(int));
   g.X[0] = (double*)b.take(xdoubles * sizeof(double));
@@ -184,7 +184,7 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b) {
   HIP_TRY(ctx, hipMemsetAsync(g.hist, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(g.hcols, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(g.cursor, 0, (size_t)(R * NK) * sizeof(int), ctx->stream));
-  HIP_TRY(ctx, hipMemsetAsync(g.counters, 0, (size_t)R * sizeof(unsigned int), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(g.counters, 0, (size_t)R * ctr::kGroupCounters * 32 * sizeof(unsigned int), ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(g.colres, 0, (size_t)std::max(g.T, 1LL) * sizeof(PanelRes), ctx->stream));
   if ((e = ctr::launch_group_schedule(ctx->imp, a, g, ctx->stream)) != hipSuccess)
     return hip_fail(ctx, e, "grouped schedule kernels");
@@ -269,8 +269,10 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
   const bool stream_ok = !*split && ctx->grid_big > 0;
   switch (want) {
     case CTR_KERNEL_AUTO:
-      if (group_ok && n_cfg >= kGroupMinBatch) *kind = Kernel::Group;
-      else if (wave_ok) *kind = Kernel::Wave;
+      // sectors <= 128 states: the per-string wavefront kernel is as fast as
+      // the grouped rounds; above, the grouped rounds win on batches
+      if (wave_ok) *kind = Kernel::Wave;
+      else if (group_ok && n_cfg >= kGroupMinBatch) *kind = Kernel::Group;
       else if (block_ok) *kind = Kernel::Block;
       else if (stream_ok) *kind = Kernel::Stream;
       else return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel can run this impurity in this precision");

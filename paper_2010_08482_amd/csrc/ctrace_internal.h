@@ -114,7 +114,7 @@ struct GroupArgs {
   int* gstart;                 // [R][NK+1] first position of every group in `sorted`
   int* istart;                 // [R][NK+1] first work item of every group
   int* n_items;                // [R]
-  unsigned int* counters;      // [R] persistent-kernel work counters
+  unsigned int* counters;      // [R][kGroupCounters * 32] persistent-kernel work counters, one per 128-byte line
   int* sorted;                 // [R][S] strings in group order
   int* colpref;                // [R][S] first column (round-relative) of every sorted string
   long long* rcols;            // [R] columns of round r
@@ -155,6 +155,9 @@ hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const Group
                               hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
 constexpr int kGroupCloseCols = 64;
+// Work items of a round are spread over this many counters (item i belongs to
+// counter i % kGroupCounters): one device-scope atomic address serialises.
+constexpr int kGroupCounters = 64;
 constexpr int kGroupPanel = 1 << 24;  // plan panel width in grouped mode: one panel per string
 
 }  // namespace ctr

@@ -311,17 +311,36 @@ def test_arena_oom_then_chunked_batches_identical(lib, ctx):
         assert np.array_equal(out["re"], ref_w["re"]) and np.array_equal(out["log_scale"], ref_w["log_scale"])
         # grouped rounds: the carried matrices do not fit, the batch is halved until they do;
         # every column's arithmetic is independent of how the batch is grouped
+        assert np.array_equal(ref["re"], ref_w["re"])  # the automatic choice here is the wavefront kernel
         mid = lib.TraceContext(tab, arena_bytes=resident + (8 << 20))
         try:
             out = mid.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
             ref_g = big.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
             assert np.array_equal(out["re"], ref_g["re"]) and np.array_equal(out["log_scale"], ref_g["log_scale"])
-            assert np.array_equal(ref["re"], ref_g["re"])  # the automatic choice for 300 traces is grouped
-            # AUTO falls back to the per-string kernel when even one configuration does not fit
-            out = small.trace_batch(cfgs)
-            assert np.array_equal(out["re"], ref_w["re"])
         finally:
             mid.close()
+        # forced grouped rounds that cannot fit one configuration: out of memory
+        with pytest.raises(lib.CtraceError) as e:
+            small.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+        assert e.value.status == -2
+    finally:
+        small.close()
+
+
+def test_auto_falls_back_when_grouped_rounds_do_not_fit(lib, ctx):
+    """f-shell (327-state sectors): AUTO takes the grouped rounds for 300 traces,
+    and the LDS workgroup kernel when the arena cannot hold their scratch."""
+    tab, big = ctx("fshell")
+    cfgs = make_configs(2, 300)
+    say("[gpu] AUTO fallback fshell x300")
+    auto = big.trace_batch(cfgs)
+    grouped = big.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+    block = big.trace_batch(cfgs, kernel=lib.CTR_KERNEL_BLOCK)
+    assert np.array_equal(auto["re"], grouped["re"]) and np.array_equal(auto["im"], grouped["im"])
+    small = lib.TraceContext(tab, arena_bytes=lib.ctr_arena_resident_bytes(big.ctx) + (1 << 20))
+    try:
+        out = small.trace_batch(cfgs)
+        assert np.array_equal(out["re"], block["re"]) and np.array_equal(out["im"], block["im"])
     finally:
         small.close()
 
