@@ -153,6 +153,116 @@ def cpu_baseline(imp, strings, seconds_budget=20.0):
     return len(done) / el, len(done), el, threads, done
 
 
+def serve_main(args):
+    """Serving mix: 256 Markov chains spread over the d-shell, f-shell (N, Jz)
+    and, with --serve-cf, crystal-field f-shell impurities; trace requests arrive
+    as a Poisson stream, each the chain's configuration after one pair
+    insertion or removal (App. D moves), orders starting from N(100, 30)
+    clipped to [2, 240].  Open loop: requests are submitted at their arrival
+    times whatever the server's state; reports the achieved throughput and the
+    latency percentiles per impurity.  Prints one JSON line."""
+    import threading
+
+    import torch
+
+    from paper_2010_08482_amd import ctrace
+    from paper_2010_08482_amd.sectors import build_sectors
+    from workloads import make_impurity
+    from workloads.configs import insert_pair, random_string, remove_pair
+
+    names = ["dshell", "fshell"] + (["fshell_cf"] if args.serve_cf else [])
+    share = [0.75, 0.25] if not args.serve_cf else [0.625, 0.25, 0.125]
+    imps = [make_impurity(n) for n in names]
+    free, _ = torch.cuda.mem_get_info(0)
+    ctxs = []
+    for imp in imps:
+        tab = build_sectors(imp)
+        print(f"[serve] {imp.name}: {tab.n_sectors} sectors, largest block {tab.max_dim}", file=sys.stderr, flush=True)
+        ctxs.append(ctrace.TraceContext(tab, scratch_bytes=int(min(free // (4 * len(imps)), 16 << 30))))
+    rng = np.random.Generator(np.random.PCG64(2024))
+    n_chains = 256
+    kind = rng.choice(len(names), size=n_chains, p=share)
+    chains = []
+    for c in range(n_chains):
+        imp = imps[kind[c]]
+        n = int(np.clip(round(rng.normal(100.0, 30.0) / 2) * 2, 2, 240))
+        chains.append(random_string(rng, imp.n_flavors, imp.beta, n, "alternating"))
+    n_req = int(args.serve_rate * args.serve_seconds)
+    t_arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n_req))
+    reqs = []
+    for i in range(n_req):
+        c = int(rng.integers(n_chains))
+        imp = imps[kind[c]]
+        s = chains[c]
+        if s.n <= 2 or (s.n + 2 <= 240 and rng.uniform() < 0.5):
+            s = insert_pair(rng, s, imp.n_flavors, imp.beta)
+        else:
+            s = remove_pair(rng, s, imp.n_flavors)
+        chains[c] = s
+        reqs.append((int(kind[c]), s))
+    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch)
+    results = []
+    done = threading.Event()
+
+    def collect():
+        while not done.is_set() or len(results) < n_req:
+            r = srv.poll(max_results=8192, wait=True)
+            results.extend(r.tolist())
+            if done.is_set() and len(r) == 0:
+                break
+
+    poller = threading.Thread(target=collect)
+    poller.start()
+    busy = 0
+    t0 = time.perf_counter()
+    for i, (k, s) in enumerate(reqs):
+        while time.perf_counter() - t0 < t_arr[i]:
+            pass
+        while srv.submit(k, i, s.tau, s.op) == ctrace.CTR_ERR_BUSY:
+            busy += 1
+    t_sub = time.perf_counter() - t0
+    srv.drain()
+    t_end = time.perf_counter() - t0
+    done.set()
+    poller.join()
+    results.extend(srv.poll(max_results=8192).tolist())
+    passes, evaluated = srv.stats()
+    srv.close()
+    lat = np.array([r[4] for r in results])
+    imp_of = np.array([r[1] for r in results])
+    bat = np.array([r[5] for r in results])
+    per = {}
+    for k, n in enumerate(names):
+        m = imp_of == k
+        if m.any():
+            per[n] = {"requests": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
+                      "p99_ms": float(np.percentile(lat[m], 99)), "mean_batch": float(bat[m].mean())}
+    line = {
+        "metric": "serving: trace requests/s with p50/p99 latency (continuous batching)",
+        "value": len(results) / t_end,
+        "unit": "trace evals/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "offered_rate": args.serve_rate,
+        "submit_seconds": t_sub,
+        "seconds": t_end,
+        "requests": n_req,
+        "completed": len(results),
+        "statuses_ok": int(sum(1 for r in results if r[2] == 0)),
+        "busy_retries": busy,
+        "device_passes": passes,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "per_impurity": per,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving mix: 256 chains, Poisson arrivals, pair insert/remove moves",
+                   "impurities": names, "chain_share": share, "max_batch": args.serve_batch},
+    }
+    for c in ctxs:
+        c.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,11 +278,20 @@ def main():
                     help="pair-insertion proposals for the lazy leg (-1 = every configuration, 0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once with a plain device copy (HBM counter calibration)")
+    ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the throughput step")
+    ap.add_argument("--serve-cf", action="store_true", help="serving mix: add the crystal-field f-shell")
+    ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="serving mix: seconds of arrivals")
+    ap.add_argument("--serve-batch", type=int, default=4096, help="serving mix: most requests per device pass")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run here has a single MI355X and the trace path has no "
               "multi-GPU leg; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
 

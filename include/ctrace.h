@@ -51,7 +51,8 @@ typedef enum {
   CTR_ERR_UNSORTED = -4,    /* tau not non-decreasing */
   CTR_ERR_RANGE = -5,       /* tau outside [0, beta) or operator code out of range */
   CTR_ERR_STATE = -6,       /* call needs ctr_set_impurity first */
-  CTR_ERR_UNSUPPORTED = -7  /* impurity or option outside what the kernels handle */
+  CTR_ERR_UNSUPPORTED = -7, /* impurity or option outside what the kernels handle */
+  CTR_ERR_BUSY = -8         /* serving: the impurity's queue is full; submit again later */
 } ctr_status;
 
 /* ctr_opts.precision */
@@ -246,6 +247,78 @@ ctr_status ctr_synchronize(ctr_ctx *ctx);
  */
 ctr_status ctr_kernel_timing(ctr_ctx *ctx, int32_t on);
 ctr_status ctr_kernel_timing_read(ctr_ctx *ctx, double *total_ms, int32_t *n_launches);
+
+/*
+ * Serving: continuous batching of trace requests from many Markov chains
+ * (Sec. 3.2: many chains share one GPU; the lazy trace of Sec. 3.3.1 decides
+ * their moves).  A server drives one or more contexts (one per impurity),
+ * each from a worker thread of its own on the context's stream, so the
+ * impurities' work overlaps on the device.  Requests are queued per impurity;
+ * whenever a worker's device pass ends it admits the requests that arrived
+ * meanwhile, in arrival order, up to max_batch and up to hbm_budget bytes of
+ * per-call scratch, and runs them as one batch (ctr_trace_batch, or
+ * ctr_trace_lazy_batch when any admitted request has a finite threshold).
+ * Every result is the value the same request gets alone, up to the rounding
+ * of the kernel the batch size selects.
+ *
+ * While a server runs, its contexts belong to it: the caller must not use
+ * them.  Destroy the server before destroying the contexts.
+ */
+typedef struct ctr_server ctr_server;
+
+typedef struct {
+  int32_t max_batch;    /* most requests per device pass and impurity (>= 1) */
+  int32_t max_pending;  /* most queued, not yet admitted requests per impurity (>= 1);
+                           ctr_server_submit returns CTR_ERR_BUSY beyond it */
+  size_t hbm_budget;    /* per-call scratch bytes a batch may occupy in its context's arena;
+                           0 = all of the arena not held by the impurity */
+} ctr_server_opts;
+
+typedef struct {
+  uint64_t tag;         /* the caller's tag of the request */
+  int32_t impurity;     /* index of its context in ctr_server_create's list */
+  int32_t status;       /* CTR_OK, or the error of the device pass that evaluated it */
+  ctr_value value;      /* as ctr_trace / ctr_trace_lazy_batch */
+  double latency_ms;    /* from ctr_server_submit to completion */
+  int32_t batch;        /* number of requests in the device pass that evaluated it */
+  int32_t reserved;
+} ctr_result;
+
+/*
+ * Starts one worker thread per context.  ctxs[n_ctx] must each have an
+ * impurity loaded.  Errors: CTR_ERR_ARG (bad options or contexts),
+ * CTR_ERR_STATE (a context without impurity).
+ */
+ctr_status ctr_server_create(ctr_ctx *const *ctxs, int32_t n_ctx, const ctr_server_opts *opts,
+                             ctr_server **out);
+
+/*
+ * Queues one trace of impurity `impurity` (the configuration is copied; the
+ * arrays may be reused on return).  log_threshold = -INFINITY asks for the
+ * plain trace; a finite value makes it a lazy request (CTR_FLAG_REJECTED when
+ * the bound is below it).  The configuration is validated here: errors
+ * CTR_ERR_ARG, CTR_ERR_RANGE, CTR_ERR_UNSORTED as ctr_trace; CTR_ERR_BUSY when
+ * max_pending requests of that impurity are waiting; CTR_ERR_STATE after
+ * ctr_server_destroy began.
+ */
+ctr_status ctr_server_submit(ctr_server *srv, int32_t impurity, uint64_t tag, int32_t n_ops, const double *tau,
+                             const int32_t *op, double log_threshold);
+
+/*
+ * Moves up to max completed results into out[] (completion order) and sets
+ * *n_out.  wait != 0 blocks until at least one result is available or no
+ * request is outstanding.
+ */
+ctr_status ctr_server_poll(ctr_server *srv, ctr_result *out, int32_t max, int32_t *n_out, int32_t wait);
+
+/* Blocks until every submitted request has completed (results stay queued for poll). */
+ctr_status ctr_server_drain(ctr_server *srv);
+
+/* Device passes run and requests evaluated so far, per server. */
+ctr_status ctr_server_stats(const ctr_server *srv, int64_t *n_passes, int64_t *n_requests);
+
+/* Stops the workers after the requests already admitted, drops the rest, frees the server. */
+void ctr_server_destroy(ctr_server *srv);
 
 #ifdef __cplusplus
 }

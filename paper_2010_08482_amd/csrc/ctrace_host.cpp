@@ -388,6 +388,19 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
 
 }  // namespace
 
+namespace ctr {
+
+bool context_loaded(const ctr_ctx* ctx) { return ctx && ctx->loaded; }
+double context_beta(const ctr_ctx* ctx) { return ctx->beta; }
+int context_nops(const ctr_ctx* ctx) { return ctx->nops; }
+size_t context_free_scratch(const ctr_ctx* ctx) { return ctx->arena_bytes - ctx->resident; }
+size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops) {
+  return scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
+         (size_t)n_ops * (sizeof(double) + sizeof(int32_t));
+}
+
+}  // namespace ctr
+
 extern "C" {
 
 const char* ctr_version(void) { return "ctrace 0.1 (gfx950, FP64 MFMA)"; }
@@ -402,6 +415,7 @@ const char* ctr_status_string(ctr_status s) {
     case CTR_ERR_RANGE: return "CTR_ERR_RANGE";
     case CTR_ERR_STATE: return "CTR_ERR_STATE";
     case CTR_ERR_UNSUPPORTED: return "CTR_ERR_UNSUPPORTED";
+    case CTR_ERR_BUSY: return "CTR_ERR_BUSY";
   }
   return "unknown status";
 }

@@ -154,6 +154,13 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
                               hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+// Context queries for the serving layer (ctrace_host.cpp); read-only after ctr_set_impurity.
+bool context_loaded(const ctr_ctx* ctx);
+double context_beta(const ctr_ctx* ctx);
+int context_nops(const ctr_ctx* ctx);
+size_t context_free_scratch(const ctr_ctx* ctx);          // arena bytes not held by the impurity
+size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops);  // per-call scratch of one configuration
+
 constexpr int kGroupCloseCols = 64;
 // Work items of a round are spread over this many counters (item i belongs to
 // counter i % kGroupCounters): one device-scope atomic address serialises.

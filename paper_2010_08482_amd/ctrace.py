@@ -48,9 +48,23 @@ class ctr_impurity(ctypes.Structure):
                 ("block_norm", ctypes.POINTER(ctypes.c_double))]
 
 
+class ctr_server_opts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+
+
+class ctr_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("impurity", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("value", ctr_value), ("latency_ms", ctypes.c_double), ("batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 VALUE_DTYPE = np.dtype([("re", "<f8"), ("im", "<f8"), ("log_scale", "<f8"), ("log_bound", "<f8"),
                         ("n_strings", "<i4"), ("flags", "<i4")])
 assert VALUE_DTYPE.itemsize == ctypes.sizeof(ctr_value)
+RESULT_DTYPE = np.dtype([("tag", "<u8"), ("impurity", "<i4"), ("status", "<i4"), ("value", VALUE_DTYPE),
+                         ("latency_ms", "<f8"), ("batch", "<i4"), ("reserved", "<i4")])
+assert RESULT_DTYPE.itemsize == ctypes.sizeof(ctr_result)
+CTR_ERR_BUSY = -8
 
 
 def _load():
@@ -78,6 +92,12 @@ def _load():
         "ctr_synchronize": (ctypes.c_int, [vp]),
         "ctr_kernel_timing": (ctypes.c_int, [vp, i32]),
         "ctr_kernel_timing_read": (ctypes.c_int, [vp, P(f64), P(i32)]),
+        "ctr_server_create": (ctypes.c_int, [P(vp), i32, P(ctr_server_opts), P(vp)]),
+        "ctr_server_submit": (ctypes.c_int, [vp, i32, ctypes.c_uint64, i32, P(f64), P(i32), f64]),
+        "ctr_server_poll": (ctypes.c_int, [vp, vp, i32, P(i32), i32]),
+        "ctr_server_drain": (ctypes.c_int, [vp]),
+        "ctr_server_stats": (ctypes.c_int, [vp, P(i64), P(i64)]),
+        "ctr_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -254,6 +274,85 @@ def ctr_kernel_timing_read(ctx):
     n = ctypes.c_int32()
     _check(ctx, _lib.ctr_kernel_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+def ctr_server_create(ctxs, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    o = ctr_server_opts(int(max_batch), int(max_pending), int(hbm_budget))
+    out = ctypes.c_void_p()
+    st = _lib.ctr_server_create(arr, len(ctxs), ctypes.byref(o), ctypes.byref(out))
+    if st != CTR_OK:
+        raise CtraceError(st, "ctr_server_create failed")
+    return out
+
+
+def ctr_server_submit(srv, impurity: int, tag: int, tau, op, log_threshold: float = -math.inf) -> int:
+    """Returns the status (CTR_OK or CTR_ERR_BUSY); raises on any other error."""
+    tau, op = _string_arrays(tau, op)
+    st = _lib.ctr_server_submit(srv, int(impurity), int(tag), int(op.size), _ptr(tau, ctypes.c_double),
+                                _ptr(op, ctypes.c_int32), float(log_threshold))
+    if st not in (CTR_OK, CTR_ERR_BUSY):
+        raise CtraceError(st, "ctr_server_submit")
+    return st
+
+
+def ctr_server_poll(srv, max_results: int = 4096, wait: bool = False) -> np.ndarray:
+    out = np.zeros(max_results, dtype=RESULT_DTYPE)
+    n = ctypes.c_int32()
+    st = _lib.ctr_server_poll(srv, out.ctypes.data, int(max_results), ctypes.byref(n), 1 if wait else 0)
+    if st != CTR_OK:
+        raise CtraceError(st, "ctr_server_poll")
+    return out[: n.value]
+
+
+def ctr_server_drain(srv) -> None:
+    st = _lib.ctr_server_drain(srv)
+    if st != CTR_OK:
+        raise CtraceError(st, "ctr_server_drain")
+
+
+def ctr_server_stats(srv):
+    """(device passes, requests evaluated)."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    st = _lib.ctr_server_stats(srv, ctypes.byref(a), ctypes.byref(b))
+    if st != CTR_OK:
+        raise CtraceError(st, "ctr_server_stats")
+    return int(a.value), int(b.value)
+
+
+def ctr_server_destroy(srv) -> None:
+    _lib.ctr_server_destroy(srv)
+
+
+class TraceServer:
+    """Continuous-batching server over TraceContexts (one worker per context)."""
+
+    def __init__(self, contexts, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0):
+        self.contexts = list(contexts)
+        self.srv = ctr_server_create([c.ctx for c in self.contexts], max_batch, max_pending, hbm_budget)
+
+    def submit(self, impurity, tag, tau, op, log_threshold=-math.inf):
+        return ctr_server_submit(self.srv, impurity, tag, tau, op, log_threshold)
+
+    def poll(self, max_results=4096, wait=False):
+        return ctr_server_poll(self.srv, max_results, wait)
+
+    def drain(self):
+        ctr_server_drain(self.srv)
+
+    def stats(self):
+        return ctr_server_stats(self.srv)
+
+    def close(self):
+        if getattr(self, "srv", None):
+            ctr_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def value_pair(v):

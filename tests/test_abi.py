@@ -45,6 +45,11 @@ def test_status_strings_and_argument_errors_without_gpu():
     # null output pointer is rejected before any device call
     lib.ctr_create.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.ctr_create(0, None, 0, None, None) == -1
+    assert lib.ctr_status_string(-8) == b"CTR_ERR_BUSY"
+    # server: bad arguments are rejected before any thread or device work
+    lib.ctr_server_create.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    out = ctypes.c_void_p()
+    assert lib.ctr_server_create(None, 1, None, ctypes.byref(out)) == -1 and not out.value
 
 
 def test_binding_names_match_header():

@@ -545,3 +545,96 @@ def test_fp32_split_rejects_unsupported_slices(lib, ctx):
     st = lib._lib.ctr_trace(c.ctx, 2, lib._ptr(tau, lib.ctypes.c_double), lib._ptr(op, lib.ctypes.c_int32),
                             lib.ctypes.byref(o), lib.ctypes.byref(v))
     assert st == -7
+
+
+# ---------------------------------------------------------------------------
+# serving: continuous batching over several impurities
+# ---------------------------------------------------------------------------
+
+def test_server_results_match_alone(lib, ctx):
+    """Requests for two impurities (real d-shell, complex p-shell), plain and
+    lazy, submitted from four threads while earlier ones are on the GPU: every
+    result equals the same request evaluated alone, within the parity bar."""
+    import threading
+
+    tab_d, cd = ctx("dshell")
+    tab_p, cp = ctx("pshell")
+    imp_p = make_impurity("pshell")
+    rng = np.random.Generator(np.random.PCG64(31))
+    reqs = []  # (impurity, string, log threshold)
+    for s in make_configs(1, 400):
+        reqs.append((0, s, -math.inf))
+    for i in range(200):
+        reqs.append((1, random_string(rng, imp_p.n_flavors, imp_p.beta, 2 * int(rng.integers(1, 30)), "alternating"),
+                     -math.inf))
+    say("[gpu] server: reference values alone")
+    alone = []
+    for k, s, _ in reqs:
+        alone.append((cd if k == 0 else cp).trace(s.tau, s.op))
+    # every fourth d-shell request becomes lazy with a threshold around its value
+    lazy_idx = list(range(0, 400, 4))
+    for i in lazy_idx:
+        k, s, _ = reqs[i]
+        la = lib.log_abs(alone[i])
+        thr = la + float(rng.uniform(-2.0, 2.0)) if np.isfinite(la) else -1.0
+        reqs[i] = (k, s, thr)
+        alone[i] = cd.lazy_batch(np.array([0, s.n]), s.tau, s.op, np.array([thr]))[0]
+    order = rng.permutation(len(reqs))
+    srv = lib.TraceServer([cd, cp], max_batch=96)
+    try:
+        def submit(part):
+            for j in part:
+                k, s, thr = reqs[j]
+                while srv.submit(k, int(j), s.tau, s.op, thr) == lib.CTR_ERR_BUSY:
+                    pass
+        say("[gpu] server: 4 submitting threads")
+        th = [threading.Thread(target=submit, args=(order[t::4],)) for t in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        srv.drain()
+        res = srv.poll(max_results=len(reqs) + 10)
+        passes, evaluated = srv.stats()
+    finally:
+        srv.close()
+    assert len(res) == len(reqs) and evaluated == len(reqs)
+    assert np.all(res["status"] == 0)
+    assert passes < len(reqs) and res["batch"].max() > 1   # requests were batched
+    say(f"server: {len(reqs)} requests in {passes} device passes, largest batch {res['batch'].max()}")
+    for r in res:
+        j = int(r["tag"])
+        k = int(r["impurity"])
+        assert k == reqs[j][0]
+        got, ref = r["value"], alone[j]
+        assert (got["flags"] & 2) == (ref["flags"] & 2), j
+        if ref["re"] == 0 and ref["im"] == 0:
+            assert got["re"] == 0 and got["im"] == 0
+            continue
+        assert rel_err(pair(got), pair(ref)) <= 1e-10, j
+    # contexts are usable again after the server is gone
+    v = cd.trace(reqs[1][1].tau, reqs[1][1].op)
+    assert np.array_equal(v["re"], alone[1]["re"])
+
+
+def test_server_rejects_invalid_and_reports_busy(lib, ctx):
+    tab, c = ctx("dshell")
+    srv = lib.TraceServer([c], max_batch=8, max_pending=1)
+    try:
+        with pytest.raises(lib.CtraceError) as e:
+            srv.submit(0, 1, [1.0, 0.5], [0, 1])
+        assert e.value.status == -4
+        with pytest.raises(lib.CtraceError) as e:
+            srv.submit(0, 2, [0.5, 1.0], [0, 99])
+        assert e.value.status == -5
+        with pytest.raises(lib.CtraceError) as e:
+            srv.submit(3, 3, [0.5, 1.0], [0, 1])
+        assert e.value.status == -1
+        s = make_configs(1, 1)[0]
+        st = [srv.submit(0, 10 + i, s.tau, s.op) for i in range(64)]
+        assert st[0] == 0 and lib.CTR_ERR_BUSY in st   # one pending slot: some submissions bounce
+        srv.drain()
+        res = srv.poll(max_results=100)
+        assert len(res) == sum(1 for x in st if x == 0)
+    finally:
+        srv.close()

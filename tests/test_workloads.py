@@ -167,3 +167,21 @@ def test_insert_pair_keeps_flavors_alternating():
             # the old string is a subsequence of the new one
             keep = np.isin(p.tau, s.tau)
             assert np.array_equal(p.op[keep], s.op)
+
+
+def test_remove_pair_keeps_flavors_alternating():
+    from workloads.configs import remove_pair
+    from workloads.impurity import IMPURITY_SHAPE
+
+    nf, beta = IMPURITY_SHAPE["fshell"]
+    rng = np.random.Generator(np.random.PCG64(78))
+    for s in make_configs(2, 100):
+        p = remove_pair(rng, s, nf)
+        assert p.n == s.n - 2
+        assert np.all(np.diff(p.tau) >= 0)
+        for f in range(nf):
+            k = p.op[(p.op >> 1) == f] & 1
+            if k.size:
+                assert np.all(k[1:] != k[:-1]) and k[0] != k[-1]
+        # the new string is a subsequence of the old one
+        assert np.all(np.isin(p.tau, s.tau))

@@ -135,3 +135,18 @@ def insert_pair(rng: np.random.Generator, s: OperatorString, n_flavors: int, bet
     op = np.concatenate([s.op, np.array([first, second], dtype=np.int32)])
     order = np.argsort(tau, kind="stable")
     return OperatorString(tau[order].astype(np.float64), op[order].astype(np.int32))
+
+
+def remove_pair(rng: np.random.Generator, s: OperatorString, n_flavors: int) -> OperatorString:
+    """Proposal of the pair removal (App. D): a flavor with operators is drawn
+    uniformly and two of its operators that are neighbours in time (cyclically)
+    are removed, which keeps the flavor alternating."""
+    flavors = [f for f in range(n_flavors) if np.any((s.op >> 1) == f)]
+    if not flavors:
+        return s
+    f = flavors[int(rng.integers(len(flavors)))]
+    idx = np.nonzero((s.op >> 1) == f)[0]
+    i = int(rng.integers(idx.size))
+    drop = {int(idx[i]), int(idx[(i + 1) % idx.size])}
+    keep = np.array([j for j in range(s.n) if j not in drop], dtype=np.int64)
+    return OperatorString(s.tau[keep].copy(), s.op[keep].astype(np.int32))
