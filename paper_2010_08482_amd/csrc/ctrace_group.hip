@@ -472,18 +472,22 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
         acc_i[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
       }
     const int ntiles = ld >> 4;
-    // A fragments of the next k-step are loaded while the current one multiplies
-    double nr[RT], ni[RT];
+    // A fragments run kPD k-steps ahead of the products (a ring of kPD slots;
+    // kPD divides the 16 k-steps of a staged chunk, so step s sits in slot s % kPD)
+    constexpr int kPD = 2;
+    double rr[kPD][RT], ri[kPD][RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      const int tile = wave + i * NW;
-      nr[i] = ni[i] = 0.0;
-      if (tile < ntiles) {
-        const long long a = (long long)lq * ld + tile * 16 + ln;
-        nr[i] = Fr[a];
-        if (CPLX) ni[i] = Fi[a];
+    for (int d = 0; d < kPD; ++d)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = wave + i * NW;
+        rr[d][i] = ri[d][i] = 0.0;
+        if (tile < ntiles && 4 * d < kp) {
+          const long long a = (long long)(4 * d + lq) * ld + tile * 16 + ln;
+          rr[d][i] = Fr[a];
+          if (CPLX) ri[d][i] = Fi[a];
+        }
       }
-    }
     for (int k0 = 0; k0 < kp; k0 += KC) {
       const int kc = min(KC, kp - k0);
       __syncthreads();  // previous chunk consumed; s_gcol visible
@@ -495,37 +499,43 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
         if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] : 0.0;
       }
       __syncthreads();
-      for (int kk = 0; kk < kc; kk += 4) {
-        double ar[RT], ai[RT];
+      for (int kb = 0; kb < kc; kb += 4 * kPD) {
 #pragma unroll
-        for (int i = 0; i < RT; ++i) {
-          ar[i] = nr[i];
-          ai[i] = ni[i];
-        }
-        const int kn = k0 + kk + 4;
-        if (kn < kp) {
+        for (int d = 0; d < kPD; ++d) {
+          const int kk = kb + 4 * d;
+          if (kk < kc) {
+            double ar[RT], ai[RT];
 #pragma unroll
-          for (int i = 0; i < RT; ++i) {
-            const int tile = wave + i * NW;
-            if (tile < ntiles) {
-              const long long a = (long long)(kn + lq) * ld + tile * 16 + ln;
-              nr[i] = Fr[a];
-              if (CPLX) ni[i] = Fi[a];
+            for (int i = 0; i < RT; ++i) {
+              ar[i] = rr[d][i];
+              ai[i] = ri[d][i];
             }
-          }
-        }
+            const int kn = k0 + kk + 4 * kPD;
+            if (kn < kp) {
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-          const double br = sB[(t * 16 + ln) * LDB + kk + lq];
-          const double bi = CPLX ? sB[CW * LDB + (t * 16 + ln) * LDB + kk + lq] : 0.0;
+              for (int i = 0; i < RT; ++i) {
+                const int tile = wave + i * NW;
+                if (tile < ntiles) {
+                  const long long a = (long long)(kn + lq) * ld + tile * 16 + ln;
+                  rr[d][i] = Fr[a];
+                  if (CPLX) ri[d][i] = Fi[a];
+                }
+              }
+            }
 #pragma unroll
-          for (int i = 0; i < RT; ++i) {
-            if (wave + i * NW < ntiles) {
-              acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, acc_r[i][t], 0, 0, 0);
-              if (CPLX) {
-                acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, acc_r[i][t], 0, 0, 0);
-                acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, acc_i[i][t], 0, 0, 0);
-                acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, acc_i[i][t], 0, 0, 0);
+            for (int t = 0; t < CT; ++t) {
+              const double br = sB[(t * 16 + ln) * LDB + kk + lq];
+              const double bi = CPLX ? sB[CW * LDB + (t * 16 + ln) * LDB + kk + lq] : 0.0;
+#pragma unroll
+              for (int i = 0; i < RT; ++i) {
+                if (wave + i * NW < ntiles) {
+                  acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, acc_r[i][t], 0, 0, 0);
+                  if (CPLX) {
+                    acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, acc_r[i][t], 0, 0, 0);
+                    acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, acc_i[i][t], 0, 0, 0);
+                    acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, acc_i[i][t], 0, 0, 0);
+                  }
+                }
               }
             }
           }
