@@ -85,21 +85,31 @@ def chain_kernel_name(tab, n_cfg):
     return "k_chain_big"
 
 
-# HBM-side bytes per batch launch of the d-shell step (FETCH_SIZE + WRITE_SIZE,
-# scaled by the 1 GiB copy calibration), valid only for the kernel source they
-# were measured on; any change to the kernels makes the figure stale (None).
-TRAFFIC_MEASURED = {"k_chain_wave": {"source_sha256": None, "bytes": None}}
+# HBM-side bytes per launch of the dominant kernel (FETCH_SIZE + WRITE_SIZE from
+# rocprofv3, scaled by the counters' reading for a plain 1 GiB device copy),
+# per workload, valid only for the kernel source they were measured on: any
+# change to that source makes the figure stale (reported as None).
+TRAFFIC_MEASURED = {
+    ("k_chain_wave", "dshell-kanamori-10^4-orders20-80"): {
+        "source": "ctrace_kernels.hip",
+        "sha256": "ad92808e54dbf691fd7c00a82459dd9e66a0ba28ca2a911bbb4099a4120234ad",
+        "bytes": 73.0187e9},
+    ("k_gstep", "fshell-slater-soc-10^4-orders40-160 (first 2000)"): {
+        "source": "ctrace_group.hip",
+        "sha256": "64f01753e36900d713d256784929ca4ceebe789b3940f8af8644de69a17008c0",
+        "bytes": 6.8979e9},
+}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     import hashlib
 
-    rec = TRAFFIC_MEASURED.get(kernel)
-    if not rec or not rec["source_sha256"]:
+    rec = TRAFFIC_MEASURED.get((kernel, workload))
+    if not rec:
         return None
-    src = os.path.join(ROOT, "paper_2010_08482_amd", "csrc", "ctrace_kernels.hip")
+    src = os.path.join(ROOT, "paper_2010_08482_amd", "csrc", rec["source"])
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return rec["bytes"] if sha == rec["source_sha256"] else None
+    return rec["bytes"] if sha == rec["sha256"] else None
 
 
 def lazy_leg(ctx, imp, strings, w_old):
@@ -441,7 +451,8 @@ def main():
                    "complex": bool(tab.is_complex), "precision": "FP64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": measured_traffic(chain_kernel_name(tab, n_cfg)),
+                     "traffic": measured_traffic(chain_kernel_name(tab, n_cfg),
+                                                 wl["name"] if not args.n_configs else f"{wl['name']} (first {n_cfg})"),
                      "kernel": chain_kernel_name(tab, n_cfg), "algorithmic_flop_per_launch": flops / launches_per_step,
                      "launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
