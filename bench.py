@@ -288,6 +288,8 @@ def main():
                     help="pair-insertion proposals for the lazy leg (-1 = every configuration, 0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once with a plain device copy (HBM counter calibration)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "wave", "block", "stream", "grouped"],
+                    help="chain kernel of the timed FP64 step (default: the library's automatic choice)")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the throughput step")
     ap.add_argument("--serve-cf", action="store_true", help="serving mix: add the crystal-field f-shell")
     ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
@@ -330,9 +332,13 @@ def main():
     d_out = torch.zeros(n_cfg * ctrace.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    kernel = {"auto": ctrace.CTR_KERNEL_AUTO, "wave": ctrace.CTR_KERNEL_WAVE, "block": ctrace.CTR_KERNEL_BLOCK,
+              "stream": ctrace.CTR_KERNEL_STREAM, "grouped": ctrace.CTR_KERNEL_GROUPED}[args.kernel]
+
     def step(precision=ctrace.CTR_FP64, out_buf=None):
         ctrace.ctr_trace_batch_device(ctx.ctx, n_cfg, d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
-                                      (out_buf if out_buf is not None else d_out).data_ptr(), precision)
+                                      (out_buf if out_buf is not None else d_out).data_ptr(), precision,
+                                      kernel if precision == ctrace.CTR_FP64 else ctrace.CTR_KERNEL_AUTO)
 
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
@@ -432,6 +438,11 @@ def main():
         rel = max(errs) if errs else None
 
     value = n_cfg * args.steps / elapsed
+    xr = (tab.max_dim + 15) // 16 * 16
+    grouped_name = "k_gstep_wave" if xr <= (32 if tab.is_complex else 128) else "k_gstep"
+    kname = chain_kernel_name(tab, n_cfg) if args.kernel == "auto" else {
+        "wave": "k_chain_wave", "block": "k_chain", "stream": "k_chain_big",
+        "grouped": grouped_name}[args.kernel]
     line = {
         "metric": "trace evals/sec + MFMA % peak (FP32-split vs FP64) at <=1e-10 rel err; p50/p99",
         "value": value,
@@ -451,9 +462,9 @@ def main():
                    "complex": bool(tab.is_complex), "precision": "FP64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": measured_traffic(chain_kernel_name(tab, n_cfg),
+                     "traffic": measured_traffic(kname,
                                                  wl["name"] if not args.n_configs else f"{wl['name']} (first {n_cfg})"),
-                     "kernel": chain_kernel_name(tab, n_cfg), "algorithmic_flop_per_launch": flops / launches_per_step,
+                     "kernel": kname, "algorithmic_flop_per_launch": flops / launches_per_step,
                      "launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

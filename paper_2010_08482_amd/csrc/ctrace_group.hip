@@ -625,6 +625,12 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
   const int* item_key = G.item_key + G.ritemoff[r];
   const long long rcoloff = G.rcoloff[r];
   typedef double dbl4 __attribute__((ext_vector_type(4)));
+  // propagators of the item's distinct gaps (the columns of one string share
+  // its gap): kRuns runs of equal gaps x 16 * MT rows per wavefront
+  constexpr int kRuns = 8;
+  __shared__ double s_prop[4][kRuns * 16 * MT];
+  __shared__ double s_gap[4][kRuns];
+  const int wv = threadIdx.x >> 6;
 
   // item i is served by counter i % kGroupCounters
   const int n_items = G.n_items[r];
@@ -740,6 +746,26 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
 
     // propagator of the next gap, per-column max, rescale, store
     const double* e2 = I.esh + I.eoff[s2];
+    // runs of equal gaps among the item's columns (ballot over the lanes of row quarter 0)
+    const double dt_left = __shfl(dt, (lane + 63) & 63);
+    const unsigned long long starts = __ballot(lq == 0 && live && (ln == 0 || dt != dt_left)) & 0xffffull;
+    const int n_runs = __popcll(starts);
+    const int run = __popcll(starts & ((2ull << ln) - 1)) - 1;
+    const bool tab = n_runs <= kRuns;
+    if (tab) {
+      if (lq == 0 && ((starts >> ln) & 1)) s_gap[wv][run] = dt;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int u = 0; u < n_runs; ++u) {
+        const double g = s_gap[wv][u];
+        for (int m = lane; m < ld; m += 64) s_prop[wv][u * 16 * MT + m] = (m < d_out) ? exp(-g * e2[m]) : 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const double* prop = &s_prop[wv][(run > 0 ? run : 0) * 16 * MT];
     double cm = 0.0;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -747,7 +773,7 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int m = t * 16 + 4 * q + lq;
-          const double p = (m < d_out) ? exp(-dt * e2[m]) : 0.0;
+          const double p = tab ? prop[m] : ((m < d_out) ? exp(-dt * e2[m]) : 0.0);
           acc_r[t][q] *= p;
           cm = fmax(cm, fabs(acc_r[t][q]));
           if (CPLX) {

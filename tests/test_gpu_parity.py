@@ -638,3 +638,62 @@ def test_server_rejects_invalid_and_reports_busy(lib, ctx):
         assert len(res) == sum(1 for x in st if x == 0)
     finally:
         srv.close()
+
+
+# ---------------------------------------------------------------------------
+# maximum sizes and degenerate batches
+# ---------------------------------------------------------------------------
+
+def test_maximum_operator_count_vs_oracle(lib, ctx):
+    """512 operators (the most a configuration may hold) on the 2-orbital atom
+    and 200-300 on the d-shell, every kernel that runs them, against the
+    oracle; 513 operators are refused."""
+    from oracle import DenseTrace
+
+    rng = np.random.Generator(np.random.PCG64(55))
+    for name, orders in (("kanamori2", (512, 510, 256)), ("dshell", (300, 200))):
+        tab, c = ctx(name)
+        imp = make_impurity(name)
+        dt = DenseTrace(imp)
+        strings = [random_string(rng, imp.n_flavors, imp.beta, n, "alternating") for n in orders]
+        refs = [dt.trace(s.tau, s.op) for s in strings]
+        scales = [dt.abs_scale(s.tau, s.op) for s in strings]
+        kernels = [lib.CTR_KERNEL_WAVE, lib.CTR_KERNEL_BLOCK, lib.CTR_KERNEL_STREAM, lib.CTR_KERNEL_GROUPED]
+        for k in kernels:
+            say(f"[gpu] maximum orders {name} {orders} kernel={k}")
+            out = c.trace_batch(strings, kernel=k)
+            check_against(out, refs, scales, f"{name} max orders kernel {k}")
+        assert sum(1 for r in refs if r[0] != 0) >= 1
+    tab, c = ctx("kanamori2")
+    s = random_string(rng, 4, tab.beta, 514, "alternating")
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace(s.tau[:513], s.op[:513])
+    assert e.value.status == -1
+
+
+def test_grouped_rounds_on_degenerate_batches(lib, ctx):
+    """Grouped rounds on batches whose configurations have no product step:
+    order 0 (the partition function), odd or dead strings (exact zero), and a
+    mix with ordinary ones; same values as the wavefront kernel."""
+    from workloads.configs import OperatorString
+
+    tab, c = ctx("dshell")
+    z = (np.zeros(0), np.zeros(0, dtype=np.int32))
+    odd = (np.array([1.0]), np.array([1], dtype=np.int32))
+    dead = (np.array([1.0, 2.0]), np.array([1, 1], dtype=np.int32))
+    two = (np.array([1.0, 2.0]), np.array([1, 0], dtype=np.int32))
+    for batch in ([z] * 300, [odd, dead] * 150, [z, odd, dead, two] * 75 + list(
+            (s.tau, s.op) for s in make_configs(1, 60))):
+        say(f"[gpu] grouped degenerate batch of {len(batch)}")
+        g = c.trace_batch(batch, kernel=lib.CTR_KERNEL_GROUPED)
+        w = c.trace_batch(batch, kernel=lib.CTR_KERNEL_WAVE)
+        assert np.array_equal(g["flags"], w["flags"]) and np.array_equal(g["n_strings"], w["n_strings"])
+        for a, b in zip(g, w):
+            if b["re"] == 0 and b["im"] == 0:
+                assert a["re"] == 0 and a["im"] == 0
+            else:
+                assert rel_err(pair(a), pair(b)) < 1e-12
+    with pytest.raises(lib.CtraceError) as e:
+        c.trace_batch([OperatorString(np.array([2.0, 1.0]), np.array([1, 0], dtype=np.int32))],
+                      kernel=lib.CTR_KERNEL_GROUPED)
+    assert e.value.status == -4
