@@ -273,6 +273,60 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def fp64_throughput(wl_id, n_configs, steps, warmup):
+    """FP64 throughput of another workload in the same run (device batch,
+    inputs resident, AUTO kernel): traces/s, chain time per launch and the
+    roofline figures, for the line's "also" object."""
+    import torch
+
+    from paper_2010_08482_amd import ctrace
+    from paper_2010_08482_amd.sectors import build_sectors
+    from workloads import make_configs, make_impurity
+    from workloads.configs import pack
+
+    wl = WORKLOADS[wl_id]
+    tab = build_sectors(make_impurity(wl["impurity"]))
+    strings = make_configs(wl["config_id"], n_configs or None)
+    n_cfg = len(strings)
+    name = wl["name"] if not n_configs else f"{wl['name']} (first {n_cfg})"
+    print(f"[bench] also: {name}", file=sys.stderr, flush=True)
+    free, _ = torch.cuda.mem_get_info(0)
+    ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
+    offs, tau, op = pack(strings)
+    dev = "cuda:0"
+    d_offs, d_tau, d_op = (torch.from_numpy(a).to(dev) for a in (offs, tau, op))
+    d_out = torch.zeros(n_cfg * ctrace.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+
+    def step():
+        ctrace.ctr_trace_batch_device(ctx.ctx, n_cfg, d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
+                                      d_out.data_ptr())
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctrace.ctr_kernel_timing(ctx.ctx, True)
+    ctrace.ctr_kernel_timing_read(ctx.ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    chain_ms, launches = ctrace.ctr_kernel_timing_read(ctx.ctx)
+    ctrace.ctr_kernel_timing(ctx.ctx, False)
+    ctx.close()
+    flops = algorithmic_flops(tab, strings)
+    per_launch = chain_ms / max(launches, 1)
+    lps = launches / max(steps, 1)
+    achieved = flops / lps / (per_launch * 1e-3) / 1e12 if per_launch > 0 else None
+    kname = chain_kernel_name(tab, n_cfg)
+    return name, {"value": n_cfg * steps / elapsed, "unit": "trace evals/s", "steps": steps, "warmup": warmup,
+                  "ms_per_step": elapsed / steps * 1e3, "dtype": "c128" if tab.is_complex else "f64",
+                  "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                               "frac": achieved / PEAK_FP64_TFLOPS if achieved else None,
+                               "traffic": measured_traffic(kname, name), "kernel": kname,
+                               "algorithmic_flop_per_launch": flops / lps, "launch_ms": per_launch}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +344,8 @@ def main():
                     help="copy this many MiB once with a plain device copy (HBM counter calibration)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "wave", "block", "stream", "grouped"],
                     help="chain kernel of the timed FP64 step (default: the library's automatic choice)")
+    ap.add_argument("--no-also", action="store_true",
+                    help="skip the second workload (the f-shell (N, Jz) step, reported under \"also\")")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the throughput step")
     ap.add_argument("--serve-cf", action="store_true", help="serving mix: add the crystal-field f-shell")
     ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
@@ -474,6 +530,9 @@ def main():
         "lazy": lazy,
     }
     ctx.close()
+    if not args.no_also and args.workload == 1:
+        name, rec = fp64_throughput(2, 0, 3, 1)
+        line["also"] = {name: rec}
     print(json.dumps(line), flush=True)
 
 

@@ -60,6 +60,27 @@ def random_set(name, impurity, seed, count, lo, hi):
     return {"impurity": impurity, "seed": seed, "records": out}
 
 
+def low_order_set(name, impurity, seed, orders):
+    """Full-size impurities (16384 states): a few strings of low order, the
+    most the dense oracle affords (each operator costs a 16384^3 product).
+    The operator matrices are dropped after each string to bound memory."""
+    imp = make_impurity(impurity)
+    t0 = time.time()
+    dt = DenseTrace(imp)
+    print(f"{name}: eigenbasis in {time.time() - t0:.0f}s", flush=True)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i, n in enumerate(orders):
+        s = random_string(rng, imp.n_flavors, imp.beta, n, "alternating")
+        r = record(dt, i, s)
+        r["tau"] = s.tau.tolist()
+        r["op"] = s.op.tolist()
+        out.append(r)
+        dt._ops.clear()
+        print(f"{name}: string {i + 1}/{len(orders)} (order {n}) {time.time() - t0:.0f}s", flush=True)
+    return {"impurity": impurity, "seed": seed, "records": out}
+
+
 SETS = {
     # d-shell workload strings (the benchmark's configurations), first 256
     "dshell_config1": lambda: config_set("dshell_config1", "dshell", 1, 256),
@@ -67,6 +88,9 @@ SETS = {
     "pshell_random": lambda: random_set("pshell_random", "pshell", 77, 120, 2, 60),
     "pshell_cf_random": lambda: random_set("pshell_cf_random", "pshell_cf", 78, 120, 2, 60),
     "dshell_so_random": lambda: random_set("dshell_so_random", "dshell_so", 79, 80, 2, 80),
+    # the generic f-shell impurities of the (N, Jz) and crystal-field workloads at full size
+    "fshell_low": lambda: low_order_set("fshell_low", "fshell", 81, [2, 2, 2, 4]),
+    "fshell_cf_low": lambda: low_order_set("fshell_cf_low", "fshell_cf", 82, [2, 2, 4]),
 }
 
 if __name__ == "__main__":
