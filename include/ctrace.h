@@ -72,6 +72,10 @@ typedef struct {
   double log_scale;    /* trace = (re + i im) * exp(log_scale) */
   double log_bound;    /* log of the lazy upper bound on |trace| (same units);
                           -inf when no string survives */
+  double log_abs;      /* log of the sum of the moduli of the evaluated contributions (per string
+                          and column panel), same units: |trace| <= exp(log_abs), and
+                          |trace| << exp(log_abs) marks a cancellation-dominated trace whose
+                          rounding error scales with exp(log_abs); -inf when nothing was evaluated */
   int32_t n_strings;   /* number of surviving sector strings */
   int32_t flags;       /* CTR_FLAG_* */
 } ctr_value;
@@ -234,6 +238,21 @@ ctr_status ctr_bound(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32
  * the same device kernel the traces use.
  */
 ctr_status ctr_strings(ctr_ctx *ctx, int32_t n_ops, const int32_t *op, int32_t *q0_out, int32_t *n_out);
+
+/*
+ * Autotuning of the chain kernel (the tile shapes differ: 8-column panels on
+ * 4x4x4 MFMA, 16-column panels on 16x16x4, grouped items of 16/32/64
+ * columns).  Evaluates the sample batch (host arrays, as ctr_trace_batch)
+ * once with every kernel that can run it in FP64, timing each second run with
+ * HIP events, and makes the fastest the choice of CTR_KERNEL_AUTO for FP64
+ * batches of at least n_cfg / 4 traces (smaller batches and lazy or
+ * FP32-split calls keep the built-in choice) until the next
+ * ctr_set_impurity.  *chosen (may be NULL) receives the CTR_KERNEL_* picked;
+ * ms_per_kernel (may be NULL) receives 5 entries indexed by CTR_KERNEL_*,
+ * the measured milliseconds or -1 where a kernel did not run.
+ */
+ctr_status ctr_tune(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau, const int32_t *op,
+                    int32_t *chosen, double *ms_per_kernel);
 
 /* Wait for all work enqueued by the context. */
 ctr_status ctr_synchronize(ctr_ctx *ctx);

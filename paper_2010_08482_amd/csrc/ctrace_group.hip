@@ -816,6 +816,7 @@ __global__ __launch_bounds__(256) void k_gcombine(DevImp I, BatchArgs B, GroupAr
   if (c >= B.n_cfg) return;
   ctr_value v;
   v.re = v.im = v.log_scale = 0.0;
+  v.log_abs = -INFINITY;
   const int flags = B.cfg_flags[c];
   v.flags = flags;
   v.n_strings = B.cfg_nstr[c];
@@ -835,7 +836,7 @@ __global__ __launch_bounds__(256) void k_gcombine(DevImp I, BatchArgs B, GroupAr
     }
     for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
     if (lmax > -INFINITY) {
-      double sr = 0.0, si = 0.0;
+      double sr = 0.0, si = 0.0, sa = 0.0;
       for (int q = 0; q < I.n_sec; ++q) {
         const StrRec R = recs[q];
         if (R.n_panels == 0) continue;
@@ -846,16 +847,19 @@ __global__ __launch_bounds__(256) void k_gcombine(DevImp I, BatchArgs B, GroupAr
             const double f = exp(P.e2 * ln2 - R.L - lmax);
             sr += P.re * f;
             si += P.im * f;
+            sa += hypot(P.re, P.im) * f;
           }
         }
       }
       for (int off = 32; off > 0; off >>= 1) {
         sr += __shfl_xor(sr, off);
         si += __shfl_xor(si, off);
+        sa += __shfl_xor(sa, off);
       }
       v.re = sr;
       v.im = si;
       v.log_scale = lmax - I.beta * I.E0;
+      v.log_abs = log(sa) + v.log_scale;
     }
   }
   if (lane == 0) B.out[c] = v;

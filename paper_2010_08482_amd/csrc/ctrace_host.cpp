@@ -36,6 +36,8 @@ struct ctr_ctx {
   int grid_big = 0;   // streaming kernel
   int grid_group = 0;  // block-grouped rounds, 0 = not applicable
   int cw_group = 0;    // columns per grouped work item
+  int tuned = 0;       // CTR_KERNEL_* picked by ctr_tune for FP64 batches (0 = none)
+  int tuned_min_batch = 0;
   double* xbuf = nullptr;  // the streaming kernel's per-workgroup X buffers
   unsigned int* counter = nullptr;
   bool timing = false;
@@ -269,6 +271,13 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
   const bool stream_ok = !*split && ctx->grid_big > 0;
   switch (want) {
     case CTR_KERNEL_AUTO:
+      if (ctx->tuned && !*split && !lazy && n_cfg >= ctx->tuned_min_batch) {
+        *kind = ctx->tuned == CTR_KERNEL_WAVE     ? Kernel::Wave
+                : ctx->tuned == CTR_KERNEL_BLOCK  ? Kernel::Block
+                : ctx->tuned == CTR_KERNEL_STREAM ? Kernel::Stream
+                                                  : Kernel::Group;
+        return CTR_OK;
+      }
       // sectors <= 128 states: the per-string wavefront kernel is as fast as
       // the grouped rounds; above, the grouped rounds win on batches
       if (wave_ok) *kind = Kernel::Wave;
@@ -653,6 +662,8 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
   ctx->cw_group = 0;
   ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, &ctx->cw_group);
+  ctx->tuned = 0;
+  ctx->tuned_min_batch = 0;
   ctx->xbuf = nullptr;
   if (ctx->grid_big > 0) {
     ctx->xbuf = (double*)b.take(ctr::big_xbuf_doubles(ctx->imp, ctx->grid_big) * sizeof(double));
@@ -674,6 +685,55 @@ ctr_status ctr_trace_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, 
   if ((s = check_opts(ctx, opts, &split, &kind, n_cfg)) != CTR_OK) return s;
   const bool auto_kind = !opts || opts->kernel == CTR_KERNEL_AUTO;
   return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind, nullptr, auto_kind);
+}
+
+ctr_status ctr_tune(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
+                    int32_t* chosen, double* ms_per_kernel) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if (n_cfg < 1 || !offsets) return fail(ctx, CTR_ERR_ARG, "empty sample");
+  if (ms_per_kernel)
+    for (int k = 0; k < 5; ++k) ms_per_kernel[k] = -1.0;
+  ctx->tuned = 0;
+  std::vector<ctr_value> out(n_cfg);
+  const int cands[4] = {CTR_KERNEL_WAVE, CTR_KERNEL_BLOCK, CTR_KERNEL_STREAM, CTR_KERNEL_GROUPED};
+  int best = 0;
+  double best_ms = 0.0;
+  for (int want : cands) {
+    ctr_opts o{};
+    o.kernel = want;
+    bool split = false;
+    Kernel kind = Kernel::Block;
+    if (check_opts(ctx, &o, &split, &kind, n_cfg) != CTR_OK) continue;  // not applicable here
+    ctx->err.clear();
+    if ((s = host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out.data(), nullptr, 0, false, kind)) != CTR_OK) {
+      if (s == CTR_ERR_OOM) continue;  // its scratch does not fit: not a candidate
+      return s;
+    }
+    hipEvent_t t0, t1;
+    HIP_TRY(ctx, hipEventCreate(&t0));
+    HIP_TRY(ctx, hipEventCreate(&t1));
+    HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
+    s = host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out.data(), nullptr, 0, false, kind);
+    HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(t1));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (s != CTR_OK) return s;
+    if (ms_per_kernel) ms_per_kernel[want] = ms;
+    if (!best || ms < best_ms) {
+      best = want;
+      best_ms = ms;
+    }
+  }
+  ctx->err.clear();
+  if (!best) return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel ran the sample");
+  ctx->tuned = best;
+  ctx->tuned_min_batch = std::max(1, n_cfg / 4);
+  if (chosen) *chosen = best;
+  return CTR_OK;
 }
 
 ctr_status ctr_trace(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, const ctr_opts* opts,

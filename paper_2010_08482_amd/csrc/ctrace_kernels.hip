@@ -1557,6 +1557,7 @@ __global__ __launch_bounds__(256) void k_combine(DevImp I, BatchArgs B) {
   if (c >= B.n_cfg) return;
   ctr_value v;
   v.re = v.im = v.log_scale = 0.0;
+  v.log_abs = -INFINITY;
   int flags = B.cfg_flags[c];
   if (B.log_thr != nullptr && B.cfg_rej[c]) flags |= CTR_FLAG_REJECTED;
   v.flags = flags;
@@ -1575,7 +1576,7 @@ __global__ __launch_bounds__(256) void k_combine(DevImp I, BatchArgs B) {
       }
     }
     if (lmax > -INFINITY) {
-      double sr = 0.0, si = 0.0;
+      double sr = 0.0, si = 0.0, sa = 0.0;
       for (int q = 0; q < I.n_sec; ++q) {
         const StrRec R = recs[q];
         for (int p = 0; p < R.n_panels; ++p) {
@@ -1584,12 +1585,14 @@ __global__ __launch_bounds__(256) void k_combine(DevImp I, BatchArgs B) {
             const double f = exp(P.e2 * ln2 - R.L - lmax);
             sr += P.re * f;
             si += P.im * f;
+            sa += hypot(P.re, P.im) * f;
           }
         }
       }
       v.re = sr;
       v.im = si;
       v.log_scale = lmax - I.beta * I.E0;
+      v.log_abs = log(sa) + v.log_scale;
     }
   }
   B.out[c] = v;

@@ -32,7 +32,8 @@ CTR_KERNEL_GROUPED = 4
 
 class ctr_value(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double), ("log_scale", ctypes.c_double),
-                ("log_bound", ctypes.c_double), ("n_strings", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("log_bound", ctypes.c_double), ("log_abs", ctypes.c_double), ("n_strings", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 class ctr_opts(ctypes.Structure):
@@ -58,7 +59,7 @@ class ctr_result(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-VALUE_DTYPE = np.dtype([("re", "<f8"), ("im", "<f8"), ("log_scale", "<f8"), ("log_bound", "<f8"),
+VALUE_DTYPE = np.dtype([("re", "<f8"), ("im", "<f8"), ("log_scale", "<f8"), ("log_bound", "<f8"), ("log_abs", "<f8"),
                         ("n_strings", "<i4"), ("flags", "<i4")])
 assert VALUE_DTYPE.itemsize == ctypes.sizeof(ctr_value)
 RESULT_DTYPE = np.dtype([("tag", "<u8"), ("impurity", "<i4"), ("status", "<i4"), ("value", VALUE_DTYPE),
@@ -92,6 +93,7 @@ def _load():
         "ctr_synchronize": (ctypes.c_int, [vp]),
         "ctr_kernel_timing": (ctypes.c_int, [vp, i32]),
         "ctr_kernel_timing_read": (ctypes.c_int, [vp, P(f64), P(i32)]),
+        "ctr_tune": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), P(f64)]),
         "ctr_server_create": (ctypes.c_int, [P(vp), i32, P(ctr_server_opts), P(vp)]),
         "ctr_server_submit": (ctypes.c_int, [vp, i32, ctypes.c_uint64, i32, P(f64), P(i32), f64]),
         "ctr_server_poll": (ctypes.c_int, [vp, vp, i32, P(i32), i32]),
@@ -206,7 +208,7 @@ def ctr_trace(ctx, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     o = _opts(precision, kernel)
     _check(ctx, _lib.ctr_trace(ctx, int(op.size), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
                                ctypes.byref(o), ctypes.byref(v)))
-    return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
+    return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.log_abs, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
 
 
 def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
@@ -274,6 +276,18 @@ def ctr_kernel_timing_read(ctx):
     n = ctypes.c_int32()
     _check(ctx, _lib.ctr_kernel_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+def ctr_tune(ctx, offsets, tau, op):
+    """Times every applicable FP64 chain kernel on the sample; returns
+    (chosen CTR_KERNEL_*, {kernel: milliseconds})."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    tau, op = _string_arrays(tau, op)
+    chosen = ctypes.c_int32()
+    ms = np.full(5, -1.0)
+    _check(ctx, _lib.ctr_tune(ctx, offsets.size - 1, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
+                              _ptr(op, ctypes.c_int32), ctypes.byref(chosen), _ptr(ms, ctypes.c_double)))
+    return int(chosen.value), {k: float(ms[k]) for k in range(1, 5) if ms[k] >= 0}
 
 
 def ctr_server_create(ctxs, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0):
@@ -425,6 +439,9 @@ class TraceContext:
 
     def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision, kernel)
+
+    def tune(self, offsets, tau, op):
+        return ctr_tune(self.ctx, offsets, tau, op)
 
     def bound(self, tau, op) -> float:
         return ctr_bound(self.ctx, tau, op)

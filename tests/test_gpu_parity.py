@@ -180,6 +180,29 @@ def test_config1_full_batch_device_path_vs_golden(lib, ctx):
     assert np.array_equal(host["re"], out["re"][:300]) and np.array_equal(host["log_scale"], out["log_scale"][:300])
 
 
+def test_cancellation_scale_between_trace_and_lehmann_sum(lib, ctx):
+    """log_abs (sum of the moduli of the evaluated contributions) lies between
+    log|trace| and the oracle's sum of moduli of all Lehmann terms."""
+    g = load_golden("dshell_config1")
+    tab, c = ctx("dshell")
+    recs = g["records"]
+    cfgs = make_configs(1, len(recs))
+    say("[gpu] cancellation scale dshell x256")
+    for kernel in (lib.CTR_KERNEL_WAVE, lib.CTR_KERNEL_GROUPED):
+        out = c.trace_batch(cfgs, kernel=kernel)
+        n_checked = 0
+        for v, r in zip(out, recs):
+            if v["re"] == 0 and v["im"] == 0:
+                assert v["log_abs"] == -np.inf
+                continue
+            la = lib.log_abs(v)
+            assert la <= v["log_abs"] + 1e-9
+            A = math.log(r["abs"]) + r["abs_log"] if r["abs"] > 0 else -np.inf
+            assert v["log_abs"] <= A + 1e-9
+            n_checked += 1
+        assert n_checked > 100
+
+
 @pytest.mark.parametrize("name", ["pshell_random", "pshell_cf_random", "dshell_so_random"])
 def test_complex_impurities_vs_golden(ctx, name):
     g = load_golden(name)
@@ -697,3 +720,28 @@ def test_grouped_rounds_on_degenerate_batches(lib, ctx):
         c.trace_batch([OperatorString(np.array([2.0, 1.0]), np.array([1, 0], dtype=np.int32))],
                       kernel=lib.CTR_KERNEL_GROUPED)
     assert e.value.status == -4
+
+
+def test_autotuner_picks_a_kernel_that_then_runs_under_auto(lib, ctx):
+    """ctr_tune times every FP64 chain kernel on a sample; AUTO then runs the
+    chosen one (bit-identical to forcing it) for batches of a quarter of the
+    sample or more, and the built-in choice below."""
+    tab, shared = ctx("dshell")
+    c = lib.TraceContext(tab)
+    try:
+        cfgs = make_configs(1, 600)
+        offs, tau, op = pack(cfgs)
+        say("[gpu] autotune dshell x600")
+        chosen, ms = c.tune(offs, tau, op)
+        say(f"autotune: chose {chosen}, ms {ms}")
+        assert chosen in ms and set(ms) == {1, 2, 3, 4}   # every kernel runs the d-shell
+        assert ms[chosen] == min(ms.values())
+        auto = c.trace_packed(offs, tau, op)
+        forced = c.trace_packed(offs, tau, op, kernel=chosen)
+        assert np.array_equal(auto["re"], forced["re"]) and np.array_equal(auto["log_scale"], forced["log_scale"])
+        small = make_configs(1, 40)   # below a quarter of the sample: built-in choice (wavefront)
+        a = c.trace_batch(small)
+        w = c.trace_batch(small, kernel=lib.CTR_KERNEL_WAVE)
+        assert np.array_equal(a["re"], w["re"])
+    finally:
+        c.close()
