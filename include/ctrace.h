@@ -97,7 +97,8 @@ enum {
 
 typedef struct {
   int32_t precision;   /* CTR_FP64 (default) or CTR_FP32_SPLIT */
-  int32_t slices;      /* CTR_FP32_SPLIT: slices per operand; 0 or 6 (6 slices of 8 bits) */
+  int32_t slices;      /* CTR_FP32_SPLIT: 8-bit slices per operand, 6 (also for 0) or 7; seven cut the
+                          truncation error ~256-fold for a third more FP32 products (28 instead of 21) */
   int32_t kernel;      /* CTR_KERNEL_*; a kernel that cannot run this impurity/precision
                           gives CTR_ERR_UNSUPPORTED */
   int32_t reserved;    /* must be 0 */

@@ -31,7 +31,9 @@ struct ctr_ctx {
   double beta = 0.0;
   long long max_panels_per_cfg = 0;
   int grid = 0;
-  int grid_split = 0;
+  int grid_split = 0;   // FP32-split, 6 slices
+  int grid_split7 = 0;  // FP32-split, 7 slices
+  int slices = 6;       // slices of the current FP32-split call
   int grid_wave = 0;  // wavefront-per-panel kernel (panels of 8 columns), 0 = not applicable
   int grid_big = 0;   // streaming kernel
   int grid_group = 0;  // block-grouped rounds, 0 = not applicable
@@ -226,7 +228,8 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
   switch (kind) {
     case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, ctx->grid_wave, ctx->stream); break;
     case Kernel::Block:
-      e = ctr::launch_chain(ctx->imp, a, split, split ? ctx->grid_split : ctx->grid, ctx->stream);
+      e = ctr::launch_chain(ctx->imp, a, split ? ctx->slices : 0,
+                            split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid, ctx->stream);
       break;
     case Kernel::Stream: e = ctr::launch_chain_big(ctx->imp, a, ctx->xbuf, ctx->grid_big, ctx->stream); break;
     case Kernel::Group: e = hipErrorInvalidValue; break;  // handled by enqueue_grouped
@@ -256,9 +259,10 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
   if (opts) {
     if (opts->reserved) return fail(ctx, CTR_ERR_ARG, "ctr_opts.reserved must be 0");
     if (opts->precision == CTR_FP32_SPLIT) {
-      if (opts->slices != 0 && opts->slices != 6)
-        return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT supports 6 slices of 8 bits (slices = 0 or 6)");
+      if (opts->slices != 0 && opts->slices != 6 && opts->slices != 7)
+        return fail(ctx, CTR_ERR_UNSUPPORTED, "CTR_FP32_SPLIT supports 6 or 7 slices of 8 bits (slices = 0, 6 or 7)");
       *split = true;
+      ctx->slices = opts->slices == 7 ? 7 : 6;
     } else if (opts->precision != CTR_FP64) {
       return fail(ctx, CTR_ERR_ARG, "unknown precision");
     }
@@ -267,7 +271,7 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
   }
   const bool group_ok = !*split && !lazy && ctx->grid_group > 0;
   const bool wave_ok = !*split && ctx->grid_wave > 0;
-  const bool block_ok = (*split ? ctx->grid_split : ctx->grid) > 0;
+  const bool block_ok = (*split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid) > 0;
   const bool stream_ok = !*split && ctx->grid_big > 0;
   switch (want) {
     case CTR_KERNEL_AUTO:
@@ -656,8 +660,9 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   long long mp = 0;
   for (int q = 0; q < ns; ++q) mp += (dim[q] + ctr::kWavePanelHost - 1) / ctr::kWavePanelHost;
   ctx->max_panels_per_cfg = mp;
-  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, false, nullptr);
-  ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, true, nullptr);
+  ctx->grid = ctr::chain_grid(ctx->imp, ctx->device, 0, nullptr);
+  ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, 6, nullptr);
+  ctx->grid_split7 = ctr::chain_grid(ctx->imp, ctx->device, 7, nullptr);
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
   ctx->cw_group = 0;

@@ -132,10 +132,11 @@ struct GroupArgs {
 // Launchers (ctrace_kernels.hip, ctrace_group.hip).  All enqueue on `stream`.
 hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
-hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream);
+// split: 0 = FP64 block products, 6 or 7 = FP32-split with that many 8-bit slices
+hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int split, int grid, hipStream_t stream);
 hipError_t launch_combine(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 // LDS bytes and persistent grid size of the chain kernel for this impurity; grid 0 = unsupported.
-int chain_grid(const DevImp& imp, int device, bool split, size_t* lds_bytes);
+int chain_grid(const DevImp& imp, int device, int split, size_t* lds_bytes);
 size_t chain_lds_bytes(const DevImp& imp);
 int chain_max_rows(int is_complex);
 // Wavefront-per-panel chain kernel (sectors of at most 128 states); grid 0 = not applicable.

@@ -411,29 +411,30 @@ __device__ __forceinline__ void step_narrow(int t, const double* __restrict__ Fr
 }
 
 // One chain step in FP32-split precision.  Every operand is cut into
-// kSlices integer-valued slices of kSliceBits bits (F per row, scaled by the
+// NSL (6 or 7) integer-valued slices of kSliceBits bits (F per row, scaled by the
 // row's power of two; X per column, already in (-1, 1) after the rescale):
 //   f = sum_s A_s 2^{-b s},  x = sum_t B_t 2^{-b t},  |A_s|, |B_t| < 2^b.
-// The products A_s B_t with s + t <= kSlices + 1 run on FP32 MFMA 16x16x4.
-// Slice products are integers below 2^{2b}; with at most kSlices products per
+// The products A_s B_t with s + t <= NSL + 1 run on FP32 MFMA 16x16x4.
+// Slice products are integers below 2^{2b}; with at most NSL products per
 // level and split_chunk() values of k per chunk, every partial sum stays below
 // 2^24, so the FP32 accumulation is exact.  After each chunk the level sums
 // are converted to FP64 (exact) and added with their weights 2^{-b L}; the
 // eigenvalue propagators, the rescale and the final trace stay FP64.
 constexpr int kSliceBits = 8;
-constexpr int kSlices = 6;
-// values of k per exact chunk: 40 real, 20 complex (two products per slice pair)
-template <bool CPLX>
+// values of k per exact chunk: 6 slices 40 real / 20 complex, 7 slices 36 / 16
+// (a complex level sum takes two products per slice pair)
+template <bool CPLX, int NSL>
 __host__ __device__ constexpr int split_chunk() {
-  return ((1 << (24 - 2 * kSliceBits)) / (kSlices * (CPLX ? 2 : 1))) & ~3;
+  return ((1 << (24 - 2 * kSliceBits)) / (NSL * (CPLX ? 2 : 1))) & ~3;
 }
 
 // D layout of the FP32 16x16x4 MFMA: item i of lane l is row f32_row(i, l/16), column l%16.
 __device__ __forceinline__ int f32_row(int i, int lq) { return 4 * lq + i; }
 
+template <int NSL>
 __device__ __forceinline__ void slice_digits(double v, float* d) {
 #pragma unroll
-  for (int s = 0; s < kSlices; ++s) {
+  for (int s = 0; s < NSL; ++s) {
     v *= (double)(1 << kSliceBits);
     const double a = trunc(v);
     d[s] = (float)a;
@@ -441,7 +442,7 @@ __device__ __forceinline__ void slice_digits(double v, float* d) {
   }
 }
 
-template <bool CPLX, int NW, int MAXT>
+template <bool CPLX, int NW, int MAXT, int NSL>
 __device__ __forceinline__ void step_split(int t, const double* __restrict__ Fr, const double* __restrict__ Fi,
                                            const short* __restrict__ rexp, int ld, int ntiles, int d_in,
                                            const double* pa, const double* pb, double* Xr, double* Xi,
@@ -480,36 +481,36 @@ __device__ __forceinline__ void step_split(int t, const double* __restrict__ Fr,
       ainv[tt] = (tile < ntiles) ? ldexp(1.0, -(int)rexp[tile * 16 + ln]) : 0.0;
     }
     const int ksteps = (d_in + 3) >> 2;
-    for (int k0 = 0; k0 < ksteps; k0 += split_chunk<CPLX>() / 4) {
-      const int k1 = min(ksteps, k0 + split_chunk<CPLX>() / 4);
-      flt4 lr[MAXT][kSlices], li[MAXT][kSlices];
+    for (int k0 = 0; k0 < ksteps; k0 += split_chunk<CPLX, NSL>() / 4) {
+      const int k1 = min(ksteps, k0 + split_chunk<CPLX, NSL>() / 4);
+      flt4 lr[MAXT][NSL], li[MAXT][NSL];
 #pragma unroll
       for (int tt = 0; tt < MAXT; ++tt)
 #pragma unroll
-        for (int L = 0; L < kSlices; ++L) {
+        for (int L = 0; L < NSL; ++L) {
           lr[tt][L] = flt4{0.f, 0.f, 0.f, 0.f};
           li[tt][L] = flt4{0.f, 0.f, 0.f, 0.f};
         }
       for (int kc = k0; kc < k1; ++kc) {
         const int krow = kc * 4 + lq;
-        float bxr[kSlices], bxi[kSlices];
-        slice_digits(Xr[krow * kPanel + ln], bxr);
-        if (CPLX) slice_digits(Xi[krow * kPanel + ln], bxi);
+        float bxr[NSL], bxi[NSL];
+        slice_digits<NSL>(Xr[krow * kPanel + ln], bxr);
+        if (CPLX) slice_digits<NSL>(Xi[krow * kPanel + ln], bxi);
 #pragma unroll
         for (int tt = 0; tt < MAXT; ++tt) {
           const int tile = wave + tt * NW;
           if (tile < ntiles) {
             const long long a = (long long)krow * ld + tile * 16 + ln;
-            float afr[kSlices], afi[kSlices], afn[kSlices];
-            slice_digits(Fr[a] * ainv[tt], afr);
+            float afr[NSL], afi[NSL], afn[NSL];
+            slice_digits<NSL>(Fr[a] * ainv[tt], afr);
             if (CPLX) {
-              slice_digits(Fi[a] * ainv[tt], afi);
+              slice_digits<NSL>(Fi[a] * ainv[tt], afi);
 #pragma unroll
-              for (int s2 = 0; s2 < kSlices; ++s2) afn[s2] = -afi[s2];
+              for (int s2 = 0; s2 < NSL; ++s2) afn[s2] = -afi[s2];
             }
-            // level L = s + t (slice indices from 1), kept for L <= kSlices + 1
+            // level L = s + t (slice indices from 1), kept for L <= NSL + 1
 #pragma unroll
-            for (int L = 2; L <= kSlices + 1; ++L) {
+            for (int L = 2; L <= NSL + 1; ++L) {
 #pragma unroll
               for (int s1 = 1; s1 < L; ++s1) {
                 const int t1 = L - s1;
@@ -528,7 +529,7 @@ __device__ __forceinline__ void step_split(int t, const double* __restrict__ Fr,
 #pragma unroll
       for (int tt = 0; tt < MAXT; ++tt) {
 #pragma unroll
-        for (int L = 2; L <= kSlices + 1; ++L) {
+        for (int L = 2; L <= NSL + 1; ++L) {
           const double wgt = ldexp(1.0, -kSliceBits * L);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -597,7 +598,7 @@ __device__ __forceinline__ void step_split(int t, const double* __restrict__ Fr,
   __syncthreads();
 }
 
-template <bool CPLX, int NW, int MAXT, bool SPLIT>
+template <bool CPLX, int NW, int MAXT, int SPLIT>
 __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
   extern __shared__ double lds[];
   constexpr int NT = NW * 64;
@@ -736,7 +737,7 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
           for (int r = tid; r < ld; r += NT) pb[r] = (r < d_out) ? exp(-dt2 * e[r]) : 0.0;
         }
         if (SPLIT) {
-          step_split<CPLX, NW, MAXT>(t, Fr, Fi, I.rexp + roff_cur, ld, ntiles, d_in, pa, pb, Xr, Xi, cmax, colexp,
+          step_split<CPLX, NW, MAXT, (SPLIT > 0 ? SPLIT : 6)>(t, Fr, Fi, I.rexp + roff_cur, ld, ntiles, d_in, pa, pb, Xr, Xi, cmax, colexp,
                                      col0, ncols, lane, wave, tid);
           continue;
         }
@@ -1628,13 +1629,14 @@ struct Variant {
 };
 
 template <bool CPLX, int NW, int MAXT>
-Variant make_variant(bool split) {
-  return Variant{split ? reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, true>)
-                       : reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, false>),
+Variant make_variant(int slices) {
+  return Variant{slices == 7   ? reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, 7>)
+                 : slices == 6 ? reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, 6>)
+                               : reinterpret_cast<const void*>(&k_chain<CPLX, NW, MAXT, 0>),
                  NW, MAXT, CPLX};
 }
 
-bool pick_variant(const DevImp& imp, bool split, Variant* v) {
+bool pick_variant(const DevImp& imp, int split, Variant* v) {
   const int tiles = imp.xrows / 16;
   if (imp.is_complex) {
     if (tiles <= 8) *v = make_variant<true, 4, 2>(split);
@@ -1671,7 +1673,7 @@ size_t chain_lds_bytes(const DevImp& imp) {
 
 int chain_max_rows(int is_complex) { return is_complex ? 576 : 1024; }
 
-int chain_grid(const DevImp& imp, int device, bool split, size_t* lds_bytes) {
+int chain_grid(const DevImp& imp, int device, int split, size_t* lds_bytes) {
   Variant v;
   if (!pick_variant(imp, split, &v)) return 0;
   const size_t bytes = chain_lds_bytes(imp);
@@ -1758,7 +1760,7 @@ hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf,
   return hipLaunchKernel(fn, dim3(grid), dim3(kBigWaves * 64), args, bytes, stream);
 }
 
-hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, bool split, int grid, hipStream_t stream) {
+hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int split, int grid, hipStream_t stream) {
   Variant v;
   if (!pick_variant(imp, split, &v) || grid <= 0) return hipErrorInvalidValue;
   const size_t bytes = chain_lds_bytes(imp);

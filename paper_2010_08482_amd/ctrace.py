@@ -151,10 +151,11 @@ def ctr_destroy(ctx) -> None:
     _lib.ctr_destroy(ctx)
 
 
-def _opts(precision, kernel=CTR_KERNEL_AUTO):
+def _opts(precision, kernel=CTR_KERNEL_AUTO, slices=0):
     o = ctr_opts()
     o.precision = int(precision)
     o.kernel = int(kernel)
+    o.slices = int(slices)
     return o
 
 
@@ -211,12 +212,12 @@ def ctr_trace(ctx, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.log_abs, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
 
 
-def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0):
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     tau, op = _string_arrays(tau, op)
     n = offsets.size - 1
     out = np.zeros(n, dtype=VALUE_DTYPE)
-    o = _opts(precision, kernel)
+    o = _opts(precision, kernel, slices)
     _check(ctx, _lib.ctr_trace_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
                                      _ptr(op, ctypes.c_int32), ctypes.byref(o),
                                      out.ctypes.data_as(ctypes.POINTER(ctr_value))))
@@ -224,9 +225,9 @@ def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL
 
 
 def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64,
-                           kernel=CTR_KERNEL_AUTO):
-    """Device pointers (ints); only enqueues on the context's stream."""
-    o = _opts(precision, kernel)
+                           kernel=CTR_KERNEL_AUTO, slices=0):
+    """Device pointers (ints); enqueues on the context's stream."""
+    o = _opts(precision, kernel, slices)
     _check(ctx, _lib.ctr_trace_batch_device(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
                                             ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
                                             ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
@@ -422,7 +423,7 @@ class TraceContext:
     def trace(self, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         return ctr_trace(self.ctx, tau, op, precision, kernel)
 
-    def trace_batch(self, strings, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+    def trace_batch(self, strings, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0):
         """strings: sequence of (tau, op) pairs or objects with .tau and .op."""
         taus = [np.asarray(getattr(s, "tau", s[0] if isinstance(s, tuple) else None), dtype=np.float64)
                 for s in strings]
@@ -432,10 +433,10 @@ class TraceContext:
         offs[1:] = np.cumsum([o.size for o in ops])
         tau = np.concatenate(taus) if taus else np.zeros(0)
         op = np.concatenate(ops) if ops else np.zeros(0, np.int32)
-        return ctr_trace_batch(self.ctx, offs, tau, op, precision, kernel)
+        return ctr_trace_batch(self.ctx, offs, tau, op, precision, kernel, slices)
 
-    def trace_packed(self, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
-        return ctr_trace_batch(self.ctx, offsets, tau, op, precision, kernel)
+    def trace_packed(self, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0):
+        return ctr_trace_batch(self.ctx, offsets, tau, op, precision, kernel, slices)
 
     def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision, kernel)

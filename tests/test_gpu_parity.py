@@ -546,6 +546,22 @@ def test_fp32_split_d_shell_vs_golden_and_fp64(lib, ctx):
     say(f"config1 fp32-split vs fp64 worst rel {worst:.2e}")
 
 
+def test_fp32_split_seven_slices_d_shell_vs_golden_and_fp64(lib, ctx):
+    """Seven 8-bit slices: stored oracle values, and agreement with the FP64
+    path within 1e-11 relative on every nonzero trace."""
+    tab, c = ctx("dshell")
+    g = load_golden("dshell_config1")
+    cfgs = make_configs(1, len(g["records"]))
+    say("[gpu] ctr_trace_batch FP32_SPLIT 7 slices config1 x256")
+    out = c.trace_batch(cfgs, precision=lib.CTR_FP32_SPLIT, slices=7)
+    check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                  "config1 fp32-split 7 slices vs oracle")
+    f64 = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_BLOCK)
+    worst = max(rel_err(pair(a), pair(b)) for a, b in zip(out, f64) if b["re"] != 0)
+    say(f"config1 fp32-split (7 slices) vs fp64 worst rel {worst:.2e}")
+    assert worst < 1e-11
+
+
 @pytest.mark.parametrize("name", ["pshell_random", "dshell_so_random"])
 def test_fp32_split_complex_vs_golden(lib, ctx, name):
     g = load_golden(name)
