@@ -91,8 +91,9 @@ enum {
   CTR_KERNEL_STREAM = 3,  /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
   CTR_KERNEL_GROUPED = 4  /* block-grouped rounds: all strings of the batch advance one operator per
                              round and the strings at the same block share one wide product; sectors
-                             <= 384 states, FP64, not lazy.  Synchronises the stream once per batch
-                             (to size its scratch from the number of surviving strings) */
+                             <= 384 states, FP64; lazy calls reject by the string bounds before the
+                             rounds (no refinement while strings run).  Synchronises the stream once
+                             per batch (to size its scratch from the number of surviving strings) */
 };
 
 typedef struct {

@@ -269,7 +269,8 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
     want = opts->kernel;
     if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_GROUPED) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
   }
-  const bool group_ok = !*split && !lazy && ctx->grid_group > 0;
+  // grouped rounds with a threshold: the plan's bound rejects, strings are not refined while they run
+  const bool group_ok = !*split && ctx->grid_group > 0;
   const bool wave_ok = !*split && ctx->grid_wave > 0;
   const bool block_ok = (*split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid) > 0;
   const bool stream_ok = !*split && ctx->grid_big > 0;
@@ -303,8 +304,7 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       *kind = Kernel::Stream;
       return CTR_OK;
     default:
-      if (!group_ok)
-        return fail(ctx, CTR_ERR_UNSUPPORTED, "grouped rounds need FP64, no lazy threshold and sectors <= 384 states");
+      if (!group_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "grouped rounds need FP64 and sectors <= 384 states");
       *kind = Kernel::Group;
       return CTR_OK;
   }

@@ -433,11 +433,11 @@ def test_lazy_bound_and_rejection(lib, ctx):
 
 @pytest.mark.parametrize("name,cid,count,kernel,split", [
     ("dshell", 1, 300, "auto", False), ("dshell", 1, 200, "block", False), ("dshell", 1, 200, "block", True),
-    ("pshell", 2, 200, "auto", False), ("dd_fshell_n", 3, 12, "auto", False)])
+    ("dshell", 1, 300, "grouped", False), ("pshell", 2, 200, "auto", False), ("dd_fshell_n", 3, 12, "auto", False)])
 def test_lazy_refinement_rejects_only_below_threshold(lib, ctx, name, cid, count, kernel, split):
     """Thresholds between |trace| and the plan bound: only the refined bounds
     (Frobenius norm of the running product, exact panel values) can reject."""
-    k = {"auto": lib.CTR_KERNEL_AUTO, "block": lib.CTR_KERNEL_BLOCK}[kernel]
+    k = {"auto": lib.CTR_KERNEL_AUTO, "block": lib.CTR_KERNEL_BLOCK, "grouped": lib.CTR_KERNEL_GROUPED}[kernel]
     prec = lib.CTR_FP32_SPLIT if split else lib.CTR_FP64
     tab, c = ctx(name)
     imp = make_impurity(name)
@@ -495,10 +495,6 @@ def test_kernel_option_errors(lib, ctx):
     assert e.value.status == -7
     with pytest.raises(lib.CtraceError) as e:
         c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED)
-    assert e.value.status == -7
-    offs, tau, op = pack(make_configs(1, 4))
-    with pytest.raises(lib.CtraceError) as e:
-        c.lazy_batch(offs, tau, op, np.zeros(4), kernel=lib.CTR_KERNEL_GROUPED)
     assert e.value.status == -7
     with pytest.raises(lib.CtraceError) as e:
         c.trace([0.5, 1.0], [1, 0], kernel=7)
