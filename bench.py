@@ -144,6 +144,35 @@ def lazy_leg(ctx, imp, strings, w_old):
             "speedup": t_full / t_lazy, "entry": "ctr_trace_lazy_batch vs ctr_trace_batch (host arrays)"}
 
 
+def histogram_leg(ctx, tab, imp, strings):
+    """Valence histogram (Sec. 2.3.2 estimator summed over the sectors of each
+    N, as in Sec. 4.2) of every configuration beside its trace, against the
+    traces alone, both through the host entry points."""
+    from workloads.configs import pack
+
+    n_of_sector = np.array([bin(int(st[0])).count("1") for st in tab.states], dtype=np.int32)
+    n_labels = imp.n_flavors + 1
+    offs, tau, op = pack(strings)
+    ctx.histogram(offs, tau, op, n_of_sector, n_labels)  # warm
+    t0 = time.perf_counter()
+    out, hist = ctx.histogram(offs, tau, op, n_of_sector, n_labels)
+    t_hist = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.trace_packed(offs, tau, op)
+    t_tr = time.perf_counter() - t0
+    dev = []
+    for v, h in zip(out, hist):
+        if v["re"] == 0 and v["im"] == 0:
+            continue
+        ratio = max(1.0, math.exp(v["log_abs"] - v["log_scale"] - math.log(abs(complex(v["re"], v["im"])))))
+        dev.append(abs(h.sum() - 1.0) / ratio)
+    return {"labels": "N", "n_labels": n_labels, "configurations": len(strings),
+            "values_per_s": len(strings) / t_hist, "traces_only_per_s": len(strings) / t_tr,
+            "overhead": t_hist / t_tr - 1.0,
+            "max_sum_rule_dev_over_cancellation": float(max(dev)) if dev else None,
+            "entry": "ctr_trace_histogram vs ctr_trace_batch (host arrays)"}
+
+
 def cpu_baseline(imp, strings, seconds_budget=20.0):
     """The CPU oracle (dense full-space FP64 chain) on a bounded sample."""
     from threadpoolctl import threadpool_info
@@ -340,6 +369,8 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split leg")
     ap.add_argument("--split-slices", type=int, default=7, choices=[6, 7],
                     help="8-bit slices per operand of the FP32-split leg (7 meets 1e-10 on every workload)")
+    ap.add_argument("--hist-sample", type=int, default=-1,
+                    help="configurations of the histogram leg (-1 = all, 0 = skip)")
     ap.add_argument("--lazy-sample", type=int, default=-1,
                     help="pair-insertion proposals for the lazy leg (-1 = every configuration, 0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -476,6 +507,10 @@ def main():
     if args.lazy_sample != 0:
         lazy = lazy_leg(ctx, imp, strings[: args.lazy_sample] if args.lazy_sample > 0 else strings, out)
 
+    hist = None
+    if args.hist_sample != 0:
+        hist = histogram_leg(ctx, tab, imp, strings[: args.hist_sample] if args.hist_sample > 0 else strings)
+
     # single-configuration latency through the host-pointer entry point
     lat = []
     for s in strings[: args.latency_sample]:
@@ -538,6 +573,7 @@ def main():
         "max_rel_err_vs_oracle_sample": rel,
         "fp32_split": split,
         "lazy": lazy,
+        "histogram": hist,
     }
     ctx.close()
     if not args.no_also and args.workload == 1:

@@ -229,6 +229,34 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offs
                                 const int32_t *op, const double *log_threshold, const ctr_opts *opts,
                                 ctr_value *out);
 
+/*
+ * Histogram of a conserved sector label (Sec. 2.3.2, the estimator of the
+ * impurity density matrix, tau-integrated, summed over the states of every
+ * label; Sec. 4.2, the valence histogram over N).  For configuration c and
+ * label l,
+ *
+ *   h_l(C) = beta^-1 int_0^beta w_loc(C, P_l(tau)) dtau / w_loc(C),
+ *
+ * P_l = projector onto the sectors q with sector_label[q] == l.  Such a
+ * projector commutes with H_loc, so the integral is the sum over the
+ * surviving sector strings s of w_s * (time s spends in label-l sectors),
+ * divided by beta * w_loc.
+ *
+ *  sector_label  host [n_sectors], values 0 .. n_labels-1 (CTR_ERR_RANGE otherwise)
+ *  n_labels      1 .. CTR_MAX_LABELS
+ *  out           host [n_cfg] traces, as ctr_trace_batch
+ *  hist          host [n_cfg * n_labels * 2]: h_l(C) of configuration c at
+ *                hist[2*(c*n_labels + l)] (real part) and [.. + 1] (imaginary
+ *                part; zero for real impurities).  All zeros for a
+ *                configuration whose trace is zero or invalid.
+ * The labels of a nonzero configuration sum to 1 up to rounding.  Other
+ * arguments and errors as ctr_trace_batch; any chain kernel and precision.
+ */
+#define CTR_MAX_LABELS 4096
+ctr_status ctr_trace_histogram(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau,
+                               const int32_t *op, const int32_t *sector_label, int32_t n_labels,
+                               const ctr_opts *opts, ctr_value *out, double *hist);
+
 /* Log of the lazy upper bound on |trace| for one configuration (-inf if no
  * string survives).  Host arrays. */
 ctr_status ctr_bound(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32_t *op, double *log_bound);

@@ -46,6 +46,7 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
     objs = []
     for src, extra in (("ctrace_kernels.hip", ["-x", "hip"]), ("ctrace_group.hip", ["-x", "hip"]),
+                       ("ctrace_hist.hip", ["-x", "hip"]),
                        ("ctrace_host.cpp", ["-x", "hip"]), ("ctrace_server.cpp", ["-x", "hip"])):
         obj = os.path.join(BUILD, src + ".o")
         _run([cc, *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(SRC, src), "-o", obj], verbose)

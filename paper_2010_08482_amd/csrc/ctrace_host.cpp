@@ -128,7 +128,7 @@ constexpr int kGroupMinBatch = 256;
 // Block-grouped rounds for the configurations of `a` (scratch after `b`'s
 // offset).  Returns CTR_ERR_OOM, with nothing enqueued past the plan, if the
 // carried matrices of the surviving strings do not fit the arena.
-ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b) {
+ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistArgs* hist) {
   a.panel = ctr::kGroupPanel;
   hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
@@ -208,11 +208,18 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b) {
   }
   if ((e = ctr::launch_group_combine(ctx->imp, a, g, ctx->stream)) != hipSuccess)
     return hip_fail(ctx, e, "grouped combine kernel");
+  if (hist) {
+    ctr::HistArgs h = *hist;
+    h.vals = g.colres;
+    h.colbase = g.s_colbase;
+    if ((e = ctr::launch_hist(ctx->imp, a, h, ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "histogram kernel");
+  }
   return CTR_OK;
 }
 
-ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kernel kind, Bump* b) {
-  if (kind == Kernel::Group && !plan_only) return enqueue_grouped(ctx, a, *b);
+ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kernel kind, Bump* b,
+                   const ctr::HistArgs* hist = nullptr) {
+  if (kind == Kernel::Group && !plan_only) return enqueue_grouped(ctx, a, *b, hist);
   a.panel = kind == Kernel::Wave ? ctr::kWavePanelHost : ctr::kPanel;
   hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
@@ -241,6 +248,12 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
   }
   e = ctr::launch_combine(ctx->imp, a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "combine kernel");
+  if (hist) {
+    ctr::HistArgs h = *hist;
+    h.vals = a.res;
+    h.colbase = nullptr;
+    if ((e = ctr::launch_hist(ctx->imp, a, h, ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "histogram kernel");
+  }
   return CTR_OK;
 }
 
@@ -319,9 +332,16 @@ Kernel per_string_kernel(const ctr_ctx* ctx) {
 
 // Host-pointer batch: validates, then runs arena-sized chunks; `mode` 0 =
 // traces, 1 = bounds only (out_bound), thresholds optional.
+// Label histogram requested with a host batch: host label table and output.
+struct HistReq {
+  const int32_t* label;  // [n_sec]
+  int32_t n_labels;
+  double* hist;          // [n_cfg][n_labels] complex
+};
+
 ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau, const int32_t* op,
                       const double* log_thr, ctr_value* out, double* out_bound, int mode, bool split,
-                      Kernel kind, BatchArgs* last = nullptr, bool auto_kind = false) {
+                      Kernel kind, BatchArgs* last = nullptr, bool auto_kind = false, const HistReq* hr = nullptr) {
   if (n_cfg < 0 || (n_cfg > 0 && (!offsets || (!out && !out_bound))))
     return fail(ctx, CTR_ERR_ARG, "null argument");
   if (n_cfg == 0) return CTR_OK;
@@ -332,7 +352,8 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     ctr_status s = check_config(ctx, n, tau + offsets[c], op + offsets[c], c);
     if (s != CTR_OK) return s;
   }
-  const size_t per_cfg = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64;
+  const size_t per_cfg = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
+                        (hr ? (size_t)hr->n_labels * 2 * sizeof(double) : 0);
   int32_t c0 = 0;
   int32_t cap = n_cfg;  // chunk cap, halved while the grouped rounds do not fit
   std::vector<long long> offs;
@@ -357,6 +378,15 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     int* d_op = (int*)b.take((size_t)std::max<long long>(nops, 1) * sizeof(int));
     ctr_value* d_out = (ctr_value*)b.take((size_t)m * sizeof(ctr_value));
     double* d_thr = log_thr ? (double*)b.take((size_t)m * sizeof(double)) : nullptr;
+    ctr::HistArgs h{};
+    if (hr) {
+      h.label = (const int*)b.take((size_t)ctx->n_sec * sizeof(int));
+      h.n_labels = hr->n_labels;
+      h.hist = (double*)b.take((size_t)m * hr->n_labels * 2 * sizeof(double));
+      if (!h.label || !h.hist) return fail(ctx, CTR_ERR_OOM, "arena too small");
+      HIP_TRY(ctx, hipMemcpyAsync((void*)h.label, hr->label, (size_t)ctx->n_sec * sizeof(int), hipMemcpyHostToDevice,
+                                  ctx->stream));
+    }
     if (!d_offs || !d_tau || !d_op || !d_out || (log_thr && !d_thr) || !carve(ctx, b, m, a))
       return fail(ctx, CTR_ERR_OOM, "arena too small");
     offs.resize(m + 1);
@@ -372,7 +402,7 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
     a.op = d_op;
     a.log_thr = d_thr;
     a.out = d_out;
-    ctr_status s = enqueue(ctx, a, mode == 1, split, kind, &b);
+    ctr_status s = enqueue(ctx, a, mode == 1, split, kind, &b, hr ? &h : nullptr);
     if (s == CTR_ERR_OOM && kind == Kernel::Group) {
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
       if (m > 1) {
@@ -391,6 +421,9 @@ ctr_status host_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const
       HIP_TRY(ctx, hipMemcpyAsync(out_bound + c0, a.cfg_logB, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     } else {
       HIP_TRY(ctx, hipMemcpyAsync(out + c0, d_out, m * sizeof(ctr_value), hipMemcpyDeviceToHost, ctx->stream));
+      if (hr)
+        HIP_TRY(ctx, hipMemcpyAsync(hr->hist + (size_t)c0 * hr->n_labels * 2, h.hist,
+                                    (size_t)m * hr->n_labels * 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (last) *last = a;
@@ -758,6 +791,23 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offs
   if ((s = check_opts(ctx, opts, &split, &kind, n_cfg, true)) != CTR_OK) return s;
   if (n_cfg > 0 && !log_threshold) return fail(ctx, CTR_ERR_ARG, "null log_threshold");
   return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split, kind);
+}
+
+ctr_status ctr_trace_histogram(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau,
+                               const int32_t* op, const int32_t* sector_label, int32_t n_labels,
+                               const ctr_opts* opts, ctr_value* out, double* hist) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  bool split = false;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, opts, &split, &kind, n_cfg)) != CTR_OK) return s;
+  if (!sector_label || n_labels < 1 || n_labels > CTR_MAX_LABELS) return fail(ctx, CTR_ERR_ARG, "bad label table");
+  if (n_cfg > 0 && (!hist || !out)) return fail(ctx, CTR_ERR_ARG, "null output");
+  for (int q = 0; q < ctx->n_sec; ++q)
+    if (sector_label[q] < 0 || sector_label[q] >= n_labels) return fail(ctx, CTR_ERR_RANGE, "sector label out of range");
+  const HistReq hr{sector_label, n_labels, hist};
+  const bool auto_kind = !opts || opts->kernel == CTR_KERNEL_AUTO;
+  return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind, nullptr, auto_kind, &hr);
 }
 
 ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double* log_bound) {

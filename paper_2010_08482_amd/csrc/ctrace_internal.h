@@ -129,12 +129,26 @@ struct GroupArgs {
   PanelRes* colres;            // [T] closed column values
 };
 
-// Launchers (ctrace_kernels.hip, ctrace_group.hip).  All enqueue on `stream`.
+// Label histogram of a batch (ctrace_hist.hip), after the combine kernel.
+// The values of string (c, q0) with record R are vals[colbase[cfg_off[c] +
+// R.loc_off] + j], j < R.width (grouped rounds: one value per column), or
+// vals[cfg_off[c] + R.loc_off + p], p < R.n_panels (per-string kernels:
+// one value per panel), as the combine kernels read them.
+struct HistArgs {
+  const int* label;          // [n_sec] label of every sector, 0 .. n_labels-1
+  int n_labels;
+  const PanelRes* vals;
+  const long long* colbase;  // grouped rounds: first column of every string; nullptr otherwise
+  double* hist;              // [n_cfg][n_labels] complex (re, im)
+};
+
+// Launchers (ctrace_kernels.hip, ctrace_group.hip, ctrace_hist.hip).  All enqueue on `stream`.
 hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
 // split: 0 = FP64 block products, 6 or 7 = FP32-split with that many 8-bit slices
 hipError_t launch_chain(const DevImp& imp, const BatchArgs& b, int split, int grid, hipStream_t stream);
 hipError_t launch_combine(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
+hipError_t launch_hist(const DevImp& imp, const BatchArgs& b, const HistArgs& h, hipStream_t stream);
 // LDS bytes and persistent grid size of the chain kernel for this impurity; grid 0 = unsupported.
 int chain_grid(const DevImp& imp, int device, int split, size_t* lds_bytes);
 size_t chain_lds_bytes(const DevImp& imp);

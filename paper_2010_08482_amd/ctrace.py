@@ -88,6 +88,8 @@ def _load():
         "ctr_trace_batch_device": (ctypes.c_int, [vp, i32, vp, vp, vp, P(ctr_opts), vp]),
         "ctr_trace_lazy_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(f64), P(ctr_opts),
                                                 P(ctr_value)]),
+        "ctr_trace_histogram": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), i32, P(ctr_opts),
+                                               P(ctr_value), P(f64)]),
         "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
         "ctr_strings": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32)]),
         "ctr_synchronize": (ctypes.c_int, [vp]),
@@ -244,6 +246,23 @@ def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP6
                                           _ptr(op, ctypes.c_int32), _ptr(thr, ctypes.c_double), ctypes.byref(o),
                                           out.ctypes.data_as(ctypes.POINTER(ctr_value))))
     return out
+
+
+def ctr_trace_histogram(ctx, offsets, tau, op, sector_label, n_labels, precision=CTR_FP64,
+                        kernel=CTR_KERNEL_AUTO, slices=0):
+    """(values [n_cfg] VALUE_DTYPE, hist [n_cfg, n_labels] complex128)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    tau, op = _string_arrays(tau, op)
+    lab = np.ascontiguousarray(sector_label, dtype=np.int32)
+    n = offsets.size - 1
+    out = np.zeros(n, dtype=VALUE_DTYPE)
+    hist = np.zeros((max(n, 0), int(n_labels)), dtype=np.complex128)
+    o = _opts(precision, kernel, slices)
+    _check(ctx, _lib.ctr_trace_histogram(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
+                                         _ptr(op, ctypes.c_int32), _ptr(lab, ctypes.c_int32), int(n_labels),
+                                         ctypes.byref(o), out.ctypes.data_as(ctypes.POINTER(ctr_value)),
+                                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out, hist
 
 
 def ctr_bound(ctx, tau, op) -> float:
@@ -443,6 +462,10 @@ class TraceContext:
 
     def tune(self, offsets, tau, op):
         return ctr_tune(self.ctx, offsets, tau, op)
+
+    def histogram(self, offsets, tau, op, sector_label, n_labels, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO,
+                  slices=0):
+        return ctr_trace_histogram(self.ctx, offsets, tau, op, sector_label, n_labels, precision, kernel, slices)
 
     def bound(self, tau, op) -> float:
         return ctr_bound(self.ctx, tau, op)

@@ -23,7 +23,7 @@ def test_header_declares_the_entry_points():
     for want in ("ctr_create", "ctr_destroy", "ctr_set_impurity", "ctr_trace", "ctr_trace_batch",
                  "ctr_trace_batch_device", "ctr_trace_lazy_batch", "ctr_bound", "ctr_strings",
                  "ctr_status_string", "ctr_last_error", "ctr_version", "ctr_synchronize",
-                 "ctr_arena_resident_bytes"):
+                 "ctr_arena_resident_bytes", "ctr_trace_histogram"):
         assert want in names
 
 

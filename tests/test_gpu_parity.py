@@ -55,6 +55,9 @@ def ctx(lib):
         c.close()
 
 
+HIST_KERNELS = {"wave": 1, "block": 2, "stream": 3, "grouped": 4}
+
+
 def pair(v):
     m = complex(v["re"], v["im"])
     return (m if m.imag != 0 else m.real), float(v["log_scale"])
@@ -213,6 +216,24 @@ def test_complex_impurities_vs_golden(ctx, name):
     out = c.trace_batch(strings)
     check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
                   name)
+
+
+@pytest.mark.parametrize("name,kernels", [("fshell_low", ("block", "stream", "grouped")),
+                                          ("fshell_cf_low", ("stream",))])
+def test_generic_fshell_low_orders_vs_golden(lib, ctx, name, kernels):
+    """The generic 16384-state f-shell impurities against the dense oracle at
+    the few low orders it affords (stored values), every kernel that runs them."""
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated")
+    g = load_golden(name)
+    tab, c = ctx(g["impurity"])
+    strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
+    for k in kernels:
+        say(f"[gpu] ctr_trace_batch {name} x{len(strings)} kernel={k}")
+        out = c.trace_batch(strings, kernel=HIST_KERNELS[k])
+        check_against(out, [golden_pair(r) for r in g["records"]],
+                      [(r["abs"], r["abs_log"]) for r in g["records"]], f"{name}/{k}")
 
 
 # ---------------------------------------------------------------------------
@@ -757,3 +778,150 @@ def test_autotuner_picks_a_kernel_that_then_runs_under_auto(lib, ctx):
         assert np.array_equal(a["re"], w["re"])
     finally:
         c.close()
+
+
+# ---------------------------------------------------------------------------
+# label histogram (density-matrix estimator summed over a conserved label)
+# ---------------------------------------------------------------------------
+
+def _sector_n(tab):
+    return np.array([bin(int(st[0])).count("1") for st in tab.states], dtype=np.int32)
+
+
+def _hist_strings(imp, seed, count, max_order):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = [random_string(rng, imp.n_flavors, imp.beta, 0, "alternating")]
+    for _ in range(count - 1):
+        out.append(random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, max_order // 2 + 1)),
+                                 "alternating"))
+    return out
+
+
+def _check_hist(out, hist, refs, label):
+    """refs: (h_ref, scale_ref, A/|w| of the trace) per configuration.  Bar:
+    |h - h_ref| <= 1e-10 |h_ref| + 1e-12 (scale + A/|w|).  The entries are
+    fractions of one (they sum to one), so the absolute part is measured
+    against that normalisation, times the trace's own cancellation ratio:
+    an entry whose exact value is zero moves by rounding-level couplings in
+    H_loc (the dense Hamiltonian carries ~2e-16 between states the sector
+    builder keeps apart), by far less than 1e-12 of the total."""
+    worst, bad, nz = 0.0, [], 0
+    for i, (v, h, (href, sc, ratio)) in enumerate(zip(out, hist, refs)):
+        if not np.any(href):
+            assert not np.any(h), f"{label} #{i}: oracle zero trace, gpu histogram {h}"
+            continue
+        nz += 1
+        d = np.abs(h - href)
+        tol = 1e-10 * np.abs(href) + 1e-12 * (sc + ratio)
+        worst = max(worst, float(np.max(d / np.maximum(np.abs(href), 1e-300))))
+        if np.any(d > tol):
+            bad.append((i, float(np.max(d - tol))))
+    say(f"{label}: {len(out)} configurations ({nz} nonzero), worst rel err {worst:.2e}, failures {bad[:5]}")
+    assert not bad
+    return nz
+
+
+def _oracle_hist_refs(imp, strings, state_label, n_labels):
+    from oracle import DenseTrace
+    from oracle.observables import label_histogram, label_histogram_abs, label_projectors
+
+    dt = DenseTrace(imp)
+    P = label_projectors(dt, state_label, n_labels)
+    refs = []
+    for s in strings:
+        h, w = label_histogram(dt, s.tau, s.op, P)
+        if w[0] == 0:
+            refs.append((h, np.zeros(n_labels), 0.0))
+            continue
+        a = dt.abs_scale(s.tau, s.op)
+        refs.append((h, label_histogram_abs(dt, s.tau, s.op, P), abs(a[0]) * math.exp(a[1] - w[1]) / abs(w[0])))
+    return refs
+
+
+_HIST_REFS = {}
+
+
+@pytest.mark.parametrize("name,kernel,slices", [
+    ("kanamori2", "wave", 0), ("kanamori2", "grouped", 0), ("pshell", "wave", 0), ("pshell", "block", 0),
+    ("pshell", "stream", 0), ("pshell", "grouped", 0), ("pshell", "block", 7)])
+def test_valence_histogram_vs_oracle(lib, ctx, name, kernel, slices):
+    """h_N of random configurations (order 0 included) against the oracle's
+    projector insertion in every interval; bar as in _check_hist."""
+    from oracle.fock import occupations
+
+    tab, c = ctx(name)
+    imp = make_impurity(name)
+    strings = _hist_strings(imp, 401, 40, 12)
+    n_labels = imp.n_flavors + 1
+    if name not in _HIST_REFS:
+        _HIST_REFS[name] = _oracle_hist_refs(imp, strings, occupations(imp.n_flavors).sum(axis=1), n_labels)
+    refs = _HIST_REFS[name]
+    offs, tau, op = pack(strings)
+    say(f"[gpu] ctr_trace_histogram {name} kernel={kernel} slices={slices} x{len(strings)}")
+    out, hist = c.histogram(offs, tau, op, _sector_n(tab), n_labels,
+                            precision=lib.CTR_FP32_SPLIT if slices else lib.CTR_FP64,
+                            kernel=HIST_KERNELS[kernel], slices=slices)
+    assert _check_hist(out, hist, refs, f"{name}/{kernel}/{slices}") >= 20
+    # order zero: the Boltzmann weights of the N sectors
+    E0 = tab.e0()
+    z = np.zeros(n_labels)
+    for q, e in enumerate(tab.energies):
+        z[_sector_n(tab)[q]] += np.sum(np.exp(-imp.beta * (np.asarray(e) - E0)))
+    assert np.max(np.abs(hist[0] - z / z.sum())) < 1e-13
+
+
+def test_histogram_over_sector_index_labels(lib, ctx):
+    """Label = sector index (more labels than one register pass holds), so
+    the histogram is the weight of every sector; compared with the oracle's
+    projectors built from the states' abelian charges."""
+    from oracle.fock import occupations
+
+    tab, c = ctx("pshell")
+    imp = make_impurity("pshell")
+    labs = occupations(imp.n_flavors) @ np.asarray(imp.qn).T
+    of = tab.sector_of_label()
+    state_sector = np.array([of[tuple(int(x) for x in row)] for row in labs])
+    strings = _hist_strings(imp, 402, 24, 8)
+    refs = _oracle_hist_refs(imp, strings, state_sector, tab.n_sectors)
+    offs, tau, op = pack(strings)
+    say(f"[gpu] ctr_trace_histogram pshell sector labels ({tab.n_sectors}) x{len(strings)}")
+    out, hist = c.histogram(offs, tau, op, np.arange(tab.n_sectors), tab.n_sectors)
+    assert tab.n_sectors > 16
+    assert _check_hist(out, hist, refs, "pshell/sector-labels") >= 12
+
+
+@pytest.mark.parametrize("name,cid,count,kernels", [("dshell", 1, 256, ("wave", "grouped")),
+                                                    ("fshell", 2, 48, ("block", "grouped"))])
+def test_histogram_full_size_sum_rule_and_kernels_agree(lib, ctx, name, cid, count, kernels):
+    """Full-size impurities: the labels of every nonzero configuration sum to
+    one, and two chain kernels agree, both within 1e-10 times the
+    configuration's cancellation ratio (sum of string moduli over |w|)."""
+    tab, c = ctx(name)
+    imp = make_impurity(name)
+    n_labels = imp.n_flavors + 1
+    offs, tau, op = pack(make_configs(cid, count))
+    res = []
+    for k in kernels:
+        say(f"[gpu] ctr_trace_histogram {name} workload {cid} x{count} kernel={k}")
+        res.append(c.histogram(offs, tau, op, _sector_n(tab), n_labels, kernel=HIST_KERNELS[k]))
+    (out, h0), (_, h1) = res
+    nz = 0
+    for i, v in enumerate(out):
+        if v["re"] == 0 and v["im"] == 0:
+            assert not np.any(h0[i]) and not np.any(h1[i])
+            continue
+        nz += 1
+        ratio = max(1.0, math.exp(v["log_abs"] - v["log_scale"] - math.log(abs(complex(v["re"], v["im"])))))
+        assert abs(h0[i].sum() - 1.0) <= 1e-10 * ratio, (i, h0[i].sum())
+        assert np.max(np.abs(h0[i] - h1[i])) <= 1e-10 * ratio, i
+    assert nz >= count // 2
+
+
+def test_histogram_argument_errors(lib, ctx):
+    tab, c = ctx("kanamori2")
+    offs, tau, op = pack(_hist_strings(make_impurity("kanamori2"), 403, 4, 4))
+    with pytest.raises(lib.CtraceError) as e:
+        c.histogram(offs, tau, op, np.full(tab.n_sectors, 5), 5)
+    assert e.value.status == -5  # CTR_ERR_RANGE: label >= n_labels
+    with pytest.raises(lib.CtraceError):
+        c.histogram(offs, tau, op, np.zeros(tab.n_sectors), 0)
