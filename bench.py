@@ -173,6 +173,44 @@ def histogram_leg(ctx, tab, imp, strings):
             "entry": "ctr_trace_histogram vs ctr_trace_batch (host arrays)"}
 
 
+def markov_leg(ctx, wl_impurity, strings, n_chains, steps):
+    """Markov steps around the trace (App. D pair moves, w_hyb fast updates on
+    the host, one lazy trace batch per step on the GPU): n_chains chains start
+    from the workload's configurations and make `steps` timed moves each."""
+    from paper_2010_08482_amd import ctrace
+    from workloads.impurity import synthetic_bath
+
+    eps, v = synthetic_bath(wl_impurity)
+    n_chains = min(n_chains, len(strings))
+    mc = ctrace.MarkovChains(ctx, n_chains, eps, v)
+    started = 0
+    for i in range(n_chains):
+        try:
+            mc.set_config(i, strings[i].tau, strings[i].op)
+            started += 1
+        except ctrace.CtraceError:
+            pass  # zero weight: the chain starts at order zero
+    rng = np.random.Generator(np.random.PCG64(4343))
+    for _ in range(3):
+        mc.step(rng.uniform(size=(n_chains, 6)))
+    s0 = mc.stats()
+    us = [rng.uniform(size=(n_chains, 6)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for u in us:
+        mc.step(u)
+    el = time.perf_counter() - t0
+    s1 = mc.stats()
+    prop = s1["proposed"] - s0["proposed"]
+    orders = [len(mc.config(i)[1]) for i in range(n_chains)]
+    mc.close()
+    return {"chains": n_chains, "started_from_workload": started, "steps": steps,
+            "moves_per_s": n_chains * steps / el, "ms_per_step": el / steps * 1e3,
+            "accepted_frac": (s1["accepted"] - s0["accepted"]) / max(prop, 1),
+            "lazy_rejected_frac": (s1["lazy_rejected"] - s0["lazy_rejected"]) / max(prop, 1),
+            "mean_order": float(np.mean(orders)),
+            "entry": "ctr_mc_step (host hybridisation updates + one ctr_trace_lazy_batch per step)"}
+
+
 def cpu_baseline(imp, strings, seconds_budget=20.0):
     """The CPU oracle (dense full-space FP64 chain) on a bounded sample."""
     from threadpoolctl import threadpool_info
@@ -369,6 +407,8 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split leg")
     ap.add_argument("--split-slices", type=int, default=7, choices=[6, 7],
                     help="8-bit slices per operand of the FP32-split leg (7 meets 1e-10 on every workload)")
+    ap.add_argument("--mc-chains", type=int, default=4096, help="chains of the Markov leg (0 = skip)")
+    ap.add_argument("--mc-steps", type=int, default=20, help="timed steps of the Markov leg")
     ap.add_argument("--hist-sample", type=int, default=-1,
                     help="configurations of the histogram leg (-1 = all, 0 = skip)")
     ap.add_argument("--lazy-sample", type=int, default=-1,
@@ -511,6 +551,10 @@ def main():
     if args.hist_sample != 0:
         hist = histogram_leg(ctx, tab, imp, strings[: args.hist_sample] if args.hist_sample > 0 else strings)
 
+    markov = None
+    if args.mc_chains > 0:
+        markov = markov_leg(ctx, wl["impurity"], strings, args.mc_chains, args.mc_steps)
+
     # single-configuration latency through the host-pointer entry point
     lat = []
     for s in strings[: args.latency_sample]:
@@ -574,6 +618,7 @@ def main():
         "fp32_split": split,
         "lazy": lazy,
         "histogram": hist,
+        "markov": markov,
     }
     ctx.close()
     if not args.no_also and args.workload == 1:

@@ -257,6 +257,68 @@ ctr_status ctr_trace_histogram(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offse
                                const int32_t *op, const int32_t *sector_label, int32_t n_labels,
                                const ctr_opts *opts, ctr_value *out, double *hist);
 
+/*
+ * Markov chains around the trace (Sec. 2.3.1 sampling; App. C
+ * Metropolis-Hastings; App. D Pauli-aware pair insertion and removal;
+ * Sec. 2.2 w_hyb).  Each chain holds a configuration, its |w_loc| and the
+ * inverse of every flavor's hybridisation block M_f[r][s] = Delta_f(tc_r -
+ * ta_s) (creators r, annihilators s), with
+ *
+ *   Delta_f(x) = -sum_k V_fk^2 exp(-x eps_fk) / (1 + exp(-beta eps_fk)),  0 < x < beta,
+ *   Delta_f(x - beta) = -Delta_f(x)            (a discrete bath per flavor).
+ *
+ * A step proposes one move per chain from six caller-drawn uniforms u[0..5]
+ * in [0, 1) (u0 < 1/2 insert, else remove; u1 flavor = floor(u1 n_f); u2 the
+ * operator after which to insert, or the first of the pair to remove, among
+ * the flavor's N operators; u3, u5 the two times inside that interval (u2,
+ * u3 scaled by beta for an empty flavor: creator at u2 beta, annihilator at
+ * u3 beta); u4 the Metropolis uniform, drawn first).  Proposal ratios:
+ * insertion N d^2 / (2 (N + 2)) (d = length of the interval), beta^2 into an
+ * empty flavor; removal the inverse of the insertion that undoes it.  The
+ * sampled weight is |w_loc w_hyb|: a move is accepted iff
+ * q |w_hyb'/w_hyb| |w_loc'| >= u4 |w_loc|.  The hybridisation ratio comes
+ * from a fast update of the inverse on the host (O(k^2)); the local traces
+ * of all chains' proposals are one ctr_trace_lazy_batch call per step with
+ * threshold log(u4 |w_loc| / (q |w_hyb'/w_hyb|)).
+ *
+ *  opts->n_chains      number of chains (>= 1); all start at order zero
+ *  opts->n_bath        levels per flavor (>= 0), bath_eps / bath_v [n_flavors * n_bath]
+ *  opts->rebuild_every accepted moves of a flavor between recomputations of its
+ *                      inverse from scratch (0: 64)
+ * The context must stay alive and loaded while the chains exist.
+ */
+typedef struct ctr_mc ctr_mc;
+typedef struct {
+  int32_t n_chains;
+  int32_t n_bath;
+  const double *bath_eps;
+  const double *bath_v;
+  int32_t rebuild_every;
+  int32_t reserved;              /* must be 0 */
+} ctr_mc_opts;
+
+/* Errors: CTR_ERR_ARG, CTR_ERR_STATE (no impurity), trace errors. */
+ctr_status ctr_mc_create(ctr_ctx *ctx, const ctr_mc_opts *opts, ctr_mc **out);
+/* Replaces chain `chain`'s configuration (host arrays, strictly increasing
+ * times, every flavor alternating between creators and annihilators).
+ * CTR_ERR_ARG if a flavor is unbalanced or not alternating, or a weight is
+ * zero; CTR_ERR_RANGE / CTR_ERR_UNSORTED as ctr_trace. */
+ctr_status ctr_mc_set_config(ctr_mc *mc, int32_t chain, int32_t n_ops, const double *tau, const int32_t *op);
+/* One move per chain.  u: host [n_chains * 6] uniforms in [0, 1)
+ * (CTR_ERR_RANGE otherwise).  decision (host [n_chains], may be NULL): 1
+ * accepted, 0 rejected, -1 no proposal (nothing to remove, coinciding times,
+ * more than 512 operators).  Synchronous. */
+ctr_status ctr_mc_step(ctr_mc *mc, const double *u, int32_t *decision);
+/* Chain `chain`'s configuration into tau/op (capacity cap; *n_ops is set even
+ * when it does not fit, then CTR_ERR_ARG) and, if log_w is not NULL,
+ * log_w[0] = log|w_loc|, log_w[1] = log|w_hyb|. */
+ctr_status ctr_mc_config(const ctr_mc *mc, int32_t chain, int32_t cap, double *tau, int32_t *op, int32_t *n_ops,
+                         double *log_w);
+/* Totals since creation: steps, proposals, proposals rejected by the lazy bound, accepted moves. */
+ctr_status ctr_mc_stats(const ctr_mc *mc, int64_t *n_steps, int64_t *n_proposed, int64_t *n_lazy_rejected,
+                        int64_t *n_accepted);
+void ctr_mc_destroy(ctr_mc *mc);
+
 /* Log of the lazy upper bound on |trace| for one configuration (-inf if no
  * string survives).  Host arrays. */
 ctr_status ctr_bound(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32_t *op, double *log_bound);

@@ -47,7 +47,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src, extra in (("ctrace_kernels.hip", ["-x", "hip"]), ("ctrace_group.hip", ["-x", "hip"]),
                        ("ctrace_hist.hip", ["-x", "hip"]),
-                       ("ctrace_host.cpp", ["-x", "hip"]), ("ctrace_server.cpp", ["-x", "hip"])):
+                       ("ctrace_host.cpp", ["-x", "hip"]), ("ctrace_server.cpp", ["-x", "hip"]),
+                       ("ctrace_mc.cpp", ["-x", "hip"])):
         obj = os.path.join(BUILD, src + ".o")
         _run([cc, *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(SRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -53,6 +53,12 @@ class ctr_server_opts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
 
 
+class ctr_mc_opts(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int32), ("n_bath", ctypes.c_int32), ("bath_eps", ctypes.POINTER(ctypes.c_double)),
+                ("bath_v", ctypes.POINTER(ctypes.c_double)), ("rebuild_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class ctr_result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("impurity", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("value", ctr_value), ("latency_ms", ctypes.c_double), ("batch", ctypes.c_int32),
@@ -102,6 +108,12 @@ def _load():
         "ctr_server_drain": (ctypes.c_int, [vp]),
         "ctr_server_stats": (ctypes.c_int, [vp, P(i64), P(i64)]),
         "ctr_server_destroy": (None, [vp]),
+        "ctr_mc_create": (ctypes.c_int, [vp, P(ctr_mc_opts), P(vp)]),
+        "ctr_mc_set_config": (ctypes.c_int, [vp, i32, i32, P(f64), P(i32)]),
+        "ctr_mc_step": (ctypes.c_int, [vp, P(f64), P(i32)]),
+        "ctr_mc_config": (ctypes.c_int, [vp, i32, i32, P(f64), P(i32), P(i32), P(f64)]),
+        "ctr_mc_stats": (ctypes.c_int, [vp, P(i64), P(i64), P(i64), P(i64)]),
+        "ctr_mc_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -356,6 +368,84 @@ def ctr_server_stats(srv):
 
 def ctr_server_destroy(srv) -> None:
     _lib.ctr_server_destroy(srv)
+
+
+def ctr_mc_create(ctx, n_chains, bath_eps, bath_v, rebuild_every=0):
+    """bath_eps, bath_v: [n_flavors, n_bath] arrays."""
+    eps = np.ascontiguousarray(bath_eps, dtype=np.float64)
+    v = np.ascontiguousarray(bath_v, dtype=np.float64)
+    o = ctr_mc_opts(int(n_chains), int(eps.shape[1]) if eps.ndim == 2 else 0, _ptr(eps, ctypes.c_double),
+                    _ptr(v, ctypes.c_double), int(rebuild_every), 0)
+    out = ctypes.c_void_p()
+    _check(ctx, _lib.ctr_mc_create(ctx, ctypes.byref(o), ctypes.byref(out)))
+    return out
+
+
+def ctr_mc_set_config(mc, chain, tau, op):
+    tau, op = _string_arrays(tau, op)
+    _check(None, _lib.ctr_mc_set_config(mc, int(chain), int(op.size), _ptr(tau, ctypes.c_double),
+                                        _ptr(op, ctypes.c_int32)))
+
+
+def ctr_mc_step(mc, u):
+    """u: [n_chains, 6] uniforms in [0, 1); returns the decisions (int32 [n_chains])."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    dec = np.zeros(u.shape[0], dtype=np.int32)
+    _check(None, _lib.ctr_mc_step(mc, _ptr(u, ctypes.c_double), _ptr(dec, ctypes.c_int32)))
+    return dec
+
+
+def ctr_mc_config(mc, chain, cap=512):
+    """(tau, op, log|w_loc|, log|w_hyb|) of one chain."""
+    tau = np.zeros(cap)
+    op = np.zeros(cap, dtype=np.int32)
+    n = ctypes.c_int32()
+    lw = np.zeros(2)
+    _check(None, _lib.ctr_mc_config(mc, int(chain), int(cap), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
+                                    ctypes.byref(n), _ptr(lw, ctypes.c_double)))
+    return tau[: n.value].copy(), op[: n.value].copy(), float(lw[0]), float(lw[1])
+
+
+def ctr_mc_stats(mc):
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(None, _lib.ctr_mc_stats(mc, *[ctypes.byref(x) for x in v]))
+    return {"steps": v[0].value, "proposed": v[1].value, "lazy_rejected": v[2].value, "accepted": v[3].value}
+
+
+def ctr_mc_destroy(mc) -> None:
+    _lib.ctr_mc_destroy(mc)
+
+
+class MarkovChains:
+    """Markov chains over one TraceContext's impurity with a discrete bath per flavor."""
+
+    def __init__(self, context, n_chains, bath_eps, bath_v, rebuild_every=0):
+        self.context = context
+        self.n_chains = int(n_chains)
+        self.mc = ctr_mc_create(context.ctx, n_chains, bath_eps, bath_v, rebuild_every)
+
+    def set_config(self, chain, tau, op):
+        ctr_mc_set_config(self.mc, chain, tau, op)
+
+    def step(self, u):
+        return ctr_mc_step(self.mc, u)
+
+    def config(self, chain):
+        return ctr_mc_config(self.mc, chain)
+
+    def stats(self):
+        return ctr_mc_stats(self.mc)
+
+    def close(self):
+        if getattr(self, "mc", None):
+            ctr_mc_destroy(self.mc)
+            self.mc = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class TraceServer:

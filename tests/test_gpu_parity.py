@@ -14,7 +14,7 @@ import pytest
 
 from tests.tracecmp import close_enough, rel_err
 from workloads import make_configs, make_impurity
-from workloads.configs import pack, random_string
+from workloads.configs import OperatorString, pack, random_string
 
 pytestmark = pytest.mark.gpu
 
@@ -925,3 +925,113 @@ def test_histogram_argument_errors(lib, ctx):
     assert e.value.status == -5  # CTR_ERR_RANGE: label >= n_labels
     with pytest.raises(lib.CtraceError):
         c.histogram(offs, tau, op, np.zeros(tab.n_sectors), 0)
+
+
+# ---------------------------------------------------------------------------
+# Markov chains around the trace (pair moves, w_hyb fast updates, lazy batch)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,n_chains,steps", [("kanamori2", 32, 300), ("pshell", 16, 150)])
+def test_markov_chains_follow_the_oracle(lib, ctx, name, n_chains, steps):
+    """Same uniforms, same decisions and configurations as the oracle's chains
+    (determinants from scratch, dense traces); a chain whose decision lies
+    within 1e-9 of its threshold is dropped from the comparison from then on."""
+    from oracle import DenseTrace
+    from oracle.markov import OracleChain
+    from workloads.impurity import synthetic_bath
+
+    tab, c = ctx(name)
+    imp = make_impurity(name)
+    eps, v = synthetic_bath(name)
+    baths = [(eps[f], v[f]) for f in range(imp.n_flavors)]
+    mc = lib.MarkovChains(c, n_chains, eps, v)
+    dt = DenseTrace(imp)
+    ref = [OracleChain(dt, baths) for _ in range(n_chains)]
+    rng = np.random.Generator(np.random.PCG64(601))
+    live = [True] * n_chains
+    ties = accepted = 0
+    say(f"[gpu] ctr_mc_step {name} {n_chains} chains x {steps} steps")
+    for step in range(steps):
+        u = rng.uniform(size=(n_chains, 6))
+        dec = mc.step(u)
+        for i in range(n_chains):
+            if not live[i]:
+                continue
+            d, margin = ref[i].step(u[i])
+            if abs(margin) < 1e-9:
+                live[i] = False
+                ties += 1
+                continue
+            assert dec[i] == d, (step, i, dec[i], d, margin)
+            accepted += d == 1
+        if step % 10 == 9 or step == steps - 1:
+            for i in range(n_chains):
+                if not live[i]:
+                    continue
+                tau, op, la_loc, la_hyb = mc.config(i)
+                assert tau.tolist() == ref[i].tau and op.tolist() == ref[i].op, (step, i)
+                assert abs(la_loc - ref[i].la_loc) <= 1e-10 * max(1.0, abs(ref[i].la_loc)), (step, i)
+                assert abs(la_hyb - ref[i].la_hyb) <= 1e-8 * max(1.0, abs(ref[i].la_hyb)), (step, i)
+    st = mc.stats()
+    say(f"{name}: accepted {accepted}, ties {ties}, stats {st}, mean order "
+        f"{np.mean([len(r.op) for r in ref]):.1f}")
+    assert ties <= 2 and accepted >= n_chains * steps // 20
+    mc.close()
+
+
+def test_markov_chains_sample_the_anderson_impurity(lib):
+    """The library's chains sample |w_loc w_hyb| of a two-flavor Anderson
+    impurity; the N histogram averaged over them equals the occupation from
+    exact diagonalisation of impurity plus bath (4 sigma over chains)."""
+    from oracle.markov import anderson_occupation
+    from paper_2010_08482_amd.sectors import build_sectors
+    from tests.test_oracle_markov import anderson_two_flavor
+
+    imp, baths = anderson_two_flavor()
+    exact = anderson_occupation(imp, baths)
+    tab = build_sectors(imp)
+    c = lib.TraceContext(tab)
+    n_chains = 512
+    eps = np.array([b[0] for b in baths])
+    v = np.array([b[1] for b in baths])
+    mc = lib.MarkovChains(c, n_chains, eps, v)
+    n_of_sector = np.array([bin(int(st[0])).count("1") for st in tab.states], dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(602))
+    say(f"[gpu] ctr_mc_step anderson {n_chains} chains")
+    for _ in range(300):
+        mc.step(rng.uniform(size=(n_chains, 6)))
+    sums = np.zeros(n_chains)
+    n_meas = 0
+    for step in range(600):
+        mc.step(rng.uniform(size=(n_chains, 6)))
+        if step % 5 == 0:
+            cfgs = [mc.config(i)[:2] for i in range(n_chains)]
+            offs, tau, op = pack([OperatorString(t, o) for t, o in cfgs])
+            _, hist = c.histogram(offs, tau, op, n_of_sector, imp.n_flavors + 1)
+            sums += np.real(hist @ np.arange(imp.n_flavors + 1))
+            n_meas += 1
+    per_chain = sums / n_meas
+    est, err = per_chain.mean(), per_chain.std(ddof=1) / math.sqrt(n_chains)
+    say(f"anderson: exact {exact:.5f}, chains {est:.5f} +- {err:.5f}, stats {mc.stats()}")
+    assert abs(est - exact) < 4 * err + 1e-3
+    mc.close()
+    c.close()
+
+
+def test_markov_chain_argument_errors(lib, ctx):
+    from workloads.impurity import synthetic_bath
+
+    tab, c = ctx("kanamori2")
+    eps, v = synthetic_bath("kanamori2")
+    mc = lib.MarkovChains(c, 4, eps, v)
+    with pytest.raises(lib.CtraceError) as e:
+        mc.step(np.full((4, 6), 1.0))
+    assert e.value.status == -5  # uniforms must lie in [0, 1)
+    with pytest.raises(lib.CtraceError):
+        mc.set_config(0, [1.0, 2.0], [1, 3])  # unbalanced flavors
+    with pytest.raises(lib.CtraceError):
+        mc.set_config(0, [1.0, 2.0, 3.0, 4.0], [1, 1, 0, 0])  # flavor 0 not alternating
+    mc.set_config(1, [1.0, 2.0], [1, 0])
+    tau, op, la_loc, la_hyb = mc.config(1)
+    assert tau.tolist() == [1.0, 2.0] and op.tolist() == [1, 0] and math.isfinite(la_loc) and math.isfinite(la_hyb)
+    mc.close()

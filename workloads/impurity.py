@@ -431,3 +431,22 @@ def make_impurity(name: str) -> Impurity:
         raise KeyError(f"unknown impurity {name!r}; known: {IMPURITY_NAMES}")
     _CACHE[name] = imp
     return imp
+
+
+# Discrete bath per flavor for the Markov step (Sec. 2.2 w_hyb): n_bath levels
+# spread over [-2, 2] with a seeded jitter, amplitudes around 0.4; every flavor
+# of an impurity gets its own draw.  Coefficients only; the hybridisation
+# function built from them lives with its users.
+BATH_LEVELS = {"kanamori2": 2, "pshell": 2, "pshell_cf": 2, "dshell": 3, "dshell_so": 3, "fshell": 3,
+               "fshell_cf": 3}
+
+
+def synthetic_bath(name: str, seed: int = 2024):
+    """(eps, v), each [n_flavors, n_bath] float64."""
+    nf, _ = IMPURITY_SHAPE[name]
+    nb = BATH_LEVELS.get(name, 2)
+    rng = np.random.Generator(np.random.PCG64([seed, sum(map(ord, name))]))
+    base = np.linspace(-2.0, 2.0, nb) if nb > 1 else np.zeros(1)
+    eps = base[None, :] + rng.normal(0.0, 0.15, (nf, nb))
+    v = 0.4 + rng.normal(0.0, 0.05, (nf, nb))
+    return eps, v
