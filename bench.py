@@ -92,12 +92,12 @@ def chain_kernel_name(tab, n_cfg):
 TRAFFIC_MEASURED = {
     ("k_chain_wave", "dshell-kanamori-10^4-orders20-80"): {
         "source": "ctrace_kernels.hip",
-        "sha256": "ad92808e54dbf691fd7c00a82459dd9e66a0ba28ca2a911bbb4099a4120234ad",
-        "bytes": 73.0187e9},
+        "sha256": "213e78688ec5b1bcafdd25921e57229a61c5a9489d9987da0d95e4da625eeaf7",
+        "bytes": 73.0208e9},
     ("k_gstep", "fshell-slater-soc-10^4-orders40-160 (first 2000)"): {
         "source": "ctrace_group.hip",
-        "sha256": "64f01753e36900d713d256784929ca4ceebe789b3940f8af8644de69a17008c0",
-        "bytes": 6.8979e9},
+        "sha256": "f732001be537306f652854790bb9ab4878fd8306f20c3a0705d3effd223d4ae0",
+        "bytes": 6.8976e9},
 }
 
 
