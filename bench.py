@@ -96,8 +96,8 @@ TRAFFIC_MEASURED = {
         "bytes": 73.0208e9},
     ("k_gstep", "fshell-slater-soc-10^4-orders40-160 (first 2000)"): {
         "source": "ctrace_group.hip",
-        "sha256": "f732001be537306f652854790bb9ab4878fd8306f20c3a0705d3effd223d4ae0",
-        "bytes": 6.8976e9},
+        "sha256": "9708edec123259f37313fe20b66e88bc7735e145da00660d37c3eedaccce5b35",
+        "bytes": 6.9142e9},
 }
 
 
@@ -194,12 +194,14 @@ def markov_leg(ctx, wl_impurity, strings, n_chains, steps):
     for _ in range(3):
         mc.step(rng.uniform(size=(n_chains, 6)))
     s0 = mc.stats()
+    h0, g0 = mc.timing()
     us = [rng.uniform(size=(n_chains, 6)) for _ in range(steps)]
     t0 = time.perf_counter()
     for u in us:
         mc.step(u)
     el = time.perf_counter() - t0
     s1 = mc.stats()
+    h1, g1 = mc.timing()
     prop = s1["proposed"] - s0["proposed"]
     orders = [len(mc.config(i)[1]) for i in range(n_chains)]
     mc.close()
@@ -208,6 +210,7 @@ def markov_leg(ctx, wl_impurity, strings, n_chains, steps):
             "accepted_frac": (s1["accepted"] - s0["accepted"]) / max(prop, 1),
             "lazy_rejected_frac": (s1["lazy_rejected"] - s0["lazy_rejected"]) / max(prop, 1),
             "mean_order": float(np.mean(orders)),
+            "host_ms_per_step": (h1 - h0) / steps, "trace_batch_ms_per_step": (g1 - g0) / steps,
             "entry": "ctr_mc_step (host hybridisation updates + one ctr_trace_lazy_batch per step)"}
 
 
@@ -228,6 +231,33 @@ def cpu_baseline(imp, strings, seconds_budget=20.0):
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") in
                    ("openblas", "mkl", "blis")] or [1])
     return len(done) / el, len(done), el, threads, done
+
+
+def cpu_block_sparse(tab, strings, seconds_budget=5.0):
+    """The same sector-block algorithm (walk, block products, trace) in NumPy
+    FP64 on the host (the tests' block reference), on a bounded sample: with
+    every BLAS thread and with one, the paper's GPU-versus-one-core setting."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from tests.blockref import block_trace
+
+    def run():
+        n, t0 = 0, time.perf_counter()
+        for s in strings:
+            block_trace(tab, s.tau, s.op)
+            n += 1
+            if time.perf_counter() - t0 > seconds_budget:
+                break
+        return n, time.perf_counter() - t0
+
+    n_all, el_all = run()
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") in
+                   ("openblas", "mkl", "blis")] or [1])
+    with threadpool_limits(limits=1):
+        n_one, el_one = run()
+    return {"value_all_cores": n_all / el_all, "cores": threads, "value_one_core": n_one / el_one,
+            "unit": "trace evals/s", "kind": "block-sparse NumPy (tests/blockref.py)",
+            "sample": f"first {n_all} / {n_one} configurations, {el_all:.1f} s / {el_one:.1f} s"}
 
 
 def serve_main(args):
@@ -359,6 +389,7 @@ def fp64_throughput(wl_id, n_configs, steps, warmup):
     print(f"[bench] also: {name}", file=sys.stderr, flush=True)
     free, _ = torch.cuda.mem_get_info(0)
     ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
+    peaks = ctrace.ctr_probe_peaks(ctx.ctx)
     offs, tau, op = pack(strings)
     dev = "cuda:0"
     d_offs, d_tau, d_op = (torch.from_numpy(a).to(dev) for a in (offs, tau, op))
@@ -453,6 +484,7 @@ def main():
     # matrix resident, so give the arena half of the free device memory (at most 64 GiB)
     free, _ = torch.cuda.mem_get_info(0)
     ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
+    peaks = ctrace.ctr_probe_peaks(ctx.ctx)
     offs, tau, op = pack(strings)
     dev = "cuda:0"
     d_offs = torch.from_numpy(offs).to(dev)
@@ -565,6 +597,7 @@ def main():
 
     cpu = None
     rel = None
+    block_sparse = None
     if not args.no_cpu:
         sample = strings[: args.cpu_sample]
         rate, done, el, threads, refs = cpu_baseline(imp, sample)
@@ -581,6 +614,7 @@ def main():
             b = complex(ref[0]) * math.exp(ref[1] - M)
             errs.append(abs(a - b) / abs(b))
         rel = max(errs) if errs else None
+        block_sparse = cpu_block_sparse(tab, strings)
 
     value = n_cfg * args.steps / elapsed
     xr = (tab.max_dim + 15) // 16 * 16
@@ -612,6 +646,8 @@ def main():
                      "kernel": kname, "algorithmic_flop_per_launch": flops / launches_per_step,
                      "launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
+        "cpu_block_sparse": block_sparse,
+        "measured_peaks": peaks,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "entry": "ctr_trace (one configuration, host pointers)"},
         "max_rel_err_vs_oracle_sample": rel,

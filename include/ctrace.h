@@ -317,6 +317,9 @@ ctr_status ctr_mc_config(const ctr_mc *mc, int32_t chain, int32_t cap, double *t
 /* Totals since creation: steps, proposals, proposals rejected by the lazy bound, accepted moves. */
 ctr_status ctr_mc_stats(const ctr_mc *mc, int64_t *n_steps, int64_t *n_proposed, int64_t *n_lazy_rejected,
                         int64_t *n_accepted);
+/* Wall time since creation spent in ctr_mc_step's host passes (proposals,
+ * hybridisation updates, batch assembly) and inside its trace batches. */
+ctr_status ctr_mc_timing(const ctr_mc *mc, double *host_ms, double *trace_ms);
 void ctr_mc_destroy(ctr_mc *mc);
 
 /* Log of the lazy upper bound on |trace| for one configuration (-inf if no
@@ -348,6 +351,18 @@ ctr_status ctr_tune(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const d
 
 /* Wait for all work enqueued by the context. */
 ctr_status ctr_synchronize(ctr_ctx *ctx);
+
+/*
+ * Measured peaks of the matrix units on the context's device (the roofline
+ * of the chain kernels, Sec. 3.3.2 names the matrix multiplication as the
+ * critical kernel): register-only loops of independent MFMA instructions,
+ * eight wavefronts per SIMD, timed with HIP events on the context's stream.
+ * out (host, 5 doubles): [0] FP64 MFMA 16x16x4 TFLOP/s, [1] FP64 MFMA 4x4x4
+ * (four blocks) TFLOP/s, [2] FP32 MFMA 16x16x4 TFLOP/s, [3] the device's
+ * reported clock in MHz, [4] compute units.  Uses 2 KiB of arena scratch.
+ * Synchronous.  Errors: CTR_ERR_ARG, CTR_ERR_OOM, CTR_ERR_DEVICE.
+ */
+ctr_status ctr_probe_peaks(ctr_ctx *ctx, double *out);
 
 /*
  * Instrumentation for roofline reports: when enabled (on != 0), every launch

@@ -893,7 +893,7 @@ bool pick_gvariant(const DevImp& imp, GVariant* v) {
   if (imp.is_complex) {
     if (tiles <= 2) *v = make_wvariant<true, 2>();
     else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
-    else if (tiles <= 24) *v = make_gvariant<true, 8, 3, 2>();
+    else if (tiles <= 24) *v = make_gvariant<true, 12, 2, 2>();  // 12 waves x 2 row tiles: 3 waves per SIMD
     else return false;
   } else {
     if (tiles <= 2) *v = make_wvariant<false, 2>();

@@ -887,6 +887,17 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
   return CTR_OK;
 }
 
+ctr_status ctr_probe_peaks(ctr_ctx* ctx, double* out) {
+  if (!ctx || !out) return CTR_ERR_ARG;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  ctx->err.clear();
+  const size_t off = align_up(ctx->resident);
+  if (off + 256 * sizeof(double) > ctx->arena_bytes) return fail(ctx, CTR_ERR_OOM, "arena too small for the probe");
+  const hipError_t e = ctr::probe_peaks(ctx->device, ctx->stream, (double*)(ctx->arena + off), out);
+  if (e != hipSuccess) return hip_fail(ctx, e, "peak probe");
+  return CTR_OK;
+}
+
 ctr_status ctr_kernel_timing(ctr_ctx* ctx, int32_t on) {
   if (!ctx) return CTR_ERR_ARG;
   ctx->timing = on != 0;

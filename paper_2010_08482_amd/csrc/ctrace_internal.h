@@ -169,6 +169,9 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
                               hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+// Peak-rate probe (ctrace_probe.hip): out[0..4] = FP64 16x16x4 and 4x4x4 MFMA and FP32 16x16x4
+// MFMA TFLOP/s, clock (MHz), compute units.  sink: 256 doubles of device memory.
+hipError_t probe_peaks(int device, hipStream_t stream, double* sink, double* out);
 // Context queries for the serving layer (ctrace_host.cpp); read-only after ctr_set_impurity.
 bool context_loaded(const ctr_ctx* ctx);
 double context_beta(const ctr_ctx* ctx);

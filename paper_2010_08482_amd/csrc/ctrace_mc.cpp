@@ -15,7 +15,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "ctrace_internal.h"
@@ -51,6 +58,79 @@ struct Move {
   std::vector<double> v, w;   // insert: inv * Q and R * inv
 };
 
+// Persistent workers for the per-chain host passes: run(n, f) calls f(i) for
+// i in [0, n) on all workers and the caller, in chunks taken from a shared
+// counter, and returns when every index is done.
+class Pool {
+ public:
+  explicit Pool(int workers) {
+    for (int w = 0; w < workers; ++w) threads_.emplace_back([this] { loop(); });
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    if (threads_.empty() || n < 64) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      f_ = &f;
+      n_ = n;
+      next_.store(0);
+      busy_ = (int)threads_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(m_);
+    done_cv_.wait(lk, [this] { return busy_ == 0; });
+    f_ = nullptr;
+  }
+
+ private:
+  static constexpr int kChunk = 32;
+  void work() {
+    for (;;) {
+      const int i0 = next_.fetch_add(kChunk);
+      if (i0 >= n_) return;
+      const int i1 = std::min(n_, i0 + kChunk);
+      for (int i = i0; i < i1; ++i) (*f_)(i);
+    }
+  }
+  void loop() {
+    long long seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+      {
+        std::lock_guard<std::mutex> lk(m_);
+        --busy_;
+      }
+      done_cv_.notify_one();
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::mutex m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* f_ = nullptr;
+  int n_ = 0, busy_ = 0;
+  long long gen_ = 0;
+  bool stop_ = false;
+  std::atomic<int> next_{0};
+};
+
 }  // namespace
 
 struct ctr_mc {
@@ -62,11 +142,17 @@ struct ctr_mc {
   std::vector<Chain> chains;
   std::vector<Move> moves;
   long long n_steps = 0, n_proposed = 0, n_lazy_rejected = 0, n_accepted = 0;
+  double host_ms = 0.0, trace_ms = 0.0;  // wall time of the host passes and of the trace batches
   // batch buffers
   std::vector<int64_t> offs;
   std::vector<double> btau, thr;
   std::vector<int32_t> bop, bchain;
   std::vector<ctr_value> out;
+  std::vector<double> thr_c;       // per chain: threshold of its proposal
+  std::vector<int64_t> len_c;      // per chain: operators of its proposal, -1 if it is not evaluated
+  std::vector<int32_t> slot_c;     // per chain: its index in the batch, -1 if none
+  std::vector<int32_t> acc_c;      // per chain: 1 if the move was accepted this step
+  std::unique_ptr<Pool> pool;
 };
 
 namespace {
@@ -231,6 +317,38 @@ void propose(const ctr_mc* mc, const Chain& C, const double* u, Move& m) {
   m.kind = 1;
 }
 
+// The proposal's operator list, written to tau/op (room for its length).
+void proposed_string_to(const Chain& C, const Move& m, int f, double* tau, int32_t* op) {
+  size_t k = 0;
+  if (m.kind == 0) {
+    const double t1 = std::min(m.tc, m.ta), t2 = std::max(m.tc, m.ta);
+    const int32_t o1 = t1 == m.tc ? 2 * f + 1 : 2 * f, o2 = t1 == m.tc ? 2 * f : 2 * f + 1;
+    size_t i = 0;
+    for (; i < C.tau.size() && C.tau[i] < t1; ++i, ++k) {
+      tau[k] = C.tau[i];
+      op[k] = C.op[i];
+    }
+    tau[k] = t1;
+    op[k++] = o1;
+    for (; i < C.tau.size() && C.tau[i] < t2; ++i, ++k) {
+      tau[k] = C.tau[i];
+      op[k] = C.op[i];
+    }
+    tau[k] = t2;
+    op[k++] = o2;
+    for (; i < C.tau.size(); ++i, ++k) {
+      tau[k] = C.tau[i];
+      op[k] = C.op[i];
+    }
+  } else {
+    for (size_t i = 0; i < C.tau.size(); ++i)
+      if ((int)i != m.ic && (int)i != m.ia) {
+        tau[k] = C.tau[i];
+        op[k++] = C.op[i];
+      }
+  }
+}
+
 // The proposal's operator list.
 void proposed_string(const Chain& C, const Move& m, int f, std::vector<double>& tau, std::vector<int32_t>& op) {
   if (m.kind == 0) {
@@ -358,6 +476,13 @@ ctr_status ctr_mc_create(ctr_ctx* ctx, const ctr_mc_opts* opts, ctr_mc** out) {
   c0.la_loc = log_abs_value(z);
   mc->chains.assign(opts->n_chains, c0);
   mc->moves.resize(opts->n_chains);
+  mc->thr_c.assign(opts->n_chains, 0.0);
+  mc->len_c.assign(opts->n_chains, -1);
+  mc->slot_c.assign(opts->n_chains, -1);
+  mc->acc_c.assign(opts->n_chains, 0);
+  // host workers: the hardware threads, at most 16, the caller being one of them
+  const int hw = (int)std::thread::hardware_concurrency();
+  mc->pool.reset(new Pool(std::max(0, std::min(hw, 16) - 1)));
   *out = mc;
   return CTR_OK;
 }
@@ -396,51 +521,78 @@ ctr_status ctr_mc_set_config(ctr_mc* mc, int32_t chain, int32_t n_ops, const dou
 
 ctr_status ctr_mc_step(ctr_mc* mc, const double* u, int32_t* decision) {
   if (!mc || !u) return CTR_ERR_ARG;
+  using Clock = std::chrono::steady_clock;
+  const Clock::time_point t0 = Clock::now();
   const int n = (int)mc->chains.size();
   for (long long i = 0; i < 6LL * n; ++i)
     if (!(u[i] >= 0.0 && u[i] < 1.0)) return CTR_ERR_RANGE;
-  mc->offs.assign(1, 0);
-  mc->btau.clear();
-  mc->bop.clear();
-  mc->thr.clear();
-  mc->bchain.clear();
-  for (int c = 0; c < n; ++c) {
-    Chain& C = mc->chains[c];
+  // pass 1, per chain: draw the move, its hybridisation ratio and its trace threshold
+  mc->pool->run(n, [&](int c) {
+    const Chain& C = mc->chains[c];
     Move& m = mc->moves[c];
     const double* uc = u + 6LL * c;
     propose(mc, C, uc, m);
-    if (decision) decision[c] = m.kind < 0 ? -1 : 0;
-    if (m.kind < 0) continue;
-    mc->n_proposed += 1;
-    if (!(std::fabs(m.ratio) > 0.0) || !std::isfinite(m.ratio)) continue;  // zero hybridisation weight
+    mc->len_c[c] = -1;
+    mc->acc_c[c] = 0;
+    if (m.kind < 0 || !(std::fabs(m.ratio) > 0.0) || !std::isfinite(m.ratio)) return;  // no trace needed
     // accept iff q |ratio| |w_loc'| >= u4 |w_loc|: the rest of the ratio goes into the trace threshold
     const double log_r = uc[4] > 0.0 ? std::log(uc[4]) : -INFINITY;
-    mc->thr.push_back(log_r + C.la_loc - std::log(m.q) - std::log(std::fabs(m.ratio)));
-    proposed_string(C, m, m.f, mc->btau, mc->bop);
-    mc->offs.push_back((int64_t)mc->bop.size());
+    mc->thr_c[c] = log_r + C.la_loc - std::log(m.q) - std::log(std::fabs(m.ratio));
+    mc->len_c[c] = (int64_t)C.op.size() + (m.kind == 0 ? 2 : -2);
+  });
+  // batch layout in chain order
+  mc->offs.assign(1, 0);
+  mc->thr.clear();
+  mc->bchain.clear();
+  for (int c = 0; c < n; ++c) {
+    if (decision) decision[c] = mc->moves[c].kind < 0 ? -1 : 0;
+    if (mc->moves[c].kind >= 0) mc->n_proposed += 1;
+    mc->slot_c[c] = -1;
+    if (mc->len_c[c] < 0) continue;
+    mc->slot_c[c] = (int32_t)mc->bchain.size();
     mc->bchain.push_back(c);
+    mc->thr.push_back(mc->thr_c[c]);
+    mc->offs.push_back(mc->offs.back() + mc->len_c[c]);
   }
   const int nb = (int)mc->bchain.size();
+  mc->btau.resize((size_t)std::max<int64_t>(mc->offs.back(), 1));
+  mc->bop.resize((size_t)std::max<int64_t>(mc->offs.back(), 1));
+  // pass 2, per proposal: its operator list into the batch
+  mc->pool->run(nb, [&](int b) {
+    const int c = mc->bchain[b];
+    const Move& m = mc->moves[c];
+    proposed_string_to(mc->chains[c], m, m.f, mc->btau.data() + mc->offs[b], mc->bop.data() + mc->offs[b]);
+  });
   mc->out.assign(nb, ctr_value{});
+  const Clock::time_point t1 = Clock::now();
   if (nb > 0) {
     const ctr_status s = ctr_trace_lazy_batch(mc->ctx, nb, mc->offs.data(), mc->btau.data(), mc->bop.data(),
                                               mc->thr.data(), nullptr, mc->out.data());
     if (s != CTR_OK) return s;
   }
-  for (int b = 0; b < nb; ++b) {
+  const Clock::time_point t2 = Clock::now();
+  // pass 3, per proposal: the decision and the update of an accepted chain
+  mc->pool->run(nb, [&](int b) {
     const int c = mc->bchain[b];
     const ctr_value& v = mc->out[b];
-    if (v.flags & CTR_FLAG_REJECTED) {
-      mc->n_lazy_rejected += 1;
-      continue;
-    }
+    if (v.flags & CTR_FLAG_REJECTED) return;
     const double la = log_abs_value(v);
-    if (!(la >= mc->thr[b]) || !std::isfinite(la)) continue;
+    if (!(la >= mc->thr[b]) || !std::isfinite(la)) return;
     commit(mc, mc->chains[c], mc->moves[c], la);
-    mc->n_accepted += 1;
-    if (decision) decision[c] = 1;
+    mc->acc_c[c] = 1;
+  });
+  for (int b = 0; b < nb; ++b) {
+    const int c = mc->bchain[b];
+    if (mc->out[b].flags & CTR_FLAG_REJECTED) mc->n_lazy_rejected += 1;
+    if (mc->acc_c[c]) {
+      mc->n_accepted += 1;
+      if (decision) decision[c] = 1;
+    }
   }
   mc->n_steps += 1;
+  const Clock::time_point t3 = Clock::now();
+  mc->host_ms += std::chrono::duration<double, std::milli>((t1 - t0) + (t3 - t2)).count();
+  mc->trace_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
   return CTR_OK;
 }
 
@@ -467,6 +619,13 @@ ctr_status ctr_mc_stats(const ctr_mc* mc, int64_t* n_steps, int64_t* n_proposed,
   *n_proposed = mc->n_proposed;
   *n_lazy_rejected = mc->n_lazy_rejected;
   *n_accepted = mc->n_accepted;
+  return CTR_OK;
+}
+
+ctr_status ctr_mc_timing(const ctr_mc* mc, double* host_ms, double* trace_ms) {
+  if (!mc || !host_ms || !trace_ms) return CTR_ERR_ARG;
+  *host_ms = mc->host_ms;
+  *trace_ms = mc->trace_ms;
   return CTR_OK;
 }
 

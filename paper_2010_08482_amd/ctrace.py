@@ -99,6 +99,7 @@ def _load():
         "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
         "ctr_strings": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32)]),
         "ctr_synchronize": (ctypes.c_int, [vp]),
+        "ctr_probe_peaks": (ctypes.c_int, [vp, P(f64)]),
         "ctr_kernel_timing": (ctypes.c_int, [vp, i32]),
         "ctr_kernel_timing_read": (ctypes.c_int, [vp, P(f64), P(i32)]),
         "ctr_tune": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), P(f64)]),
@@ -113,6 +114,7 @@ def _load():
         "ctr_mc_step": (ctypes.c_int, [vp, P(f64), P(i32)]),
         "ctr_mc_config": (ctypes.c_int, [vp, i32, i32, P(f64), P(i32), P(i32), P(f64)]),
         "ctr_mc_stats": (ctypes.c_int, [vp, P(i64), P(i64), P(i64), P(i64)]),
+        "ctr_mc_timing": (ctypes.c_int, [vp, P(f64), P(f64)]),
         "ctr_mc_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -294,6 +296,14 @@ def ctr_strings(ctx, op, n_sectors: int):
     return q0[: n.value].copy()
 
 
+def ctr_probe_peaks(ctx):
+    """Measured TFLOP/s of FP64 MFMA 16x16x4 and 4x4x4, FP32 MFMA 16x16x4; clock MHz; compute units."""
+    out = np.zeros(5)
+    _check(ctx, _lib.ctr_probe_peaks(ctx, _ptr(out, ctypes.c_double)))
+    return {"fp64_mfma_16x16x4_tflops": float(out[0]), "fp64_mfma_4x4x4_tflops": float(out[1]),
+            "fp32_mfma_16x16x4_tflops": float(out[2]), "clock_mhz": float(out[3]), "compute_units": int(out[4])}
+
+
 def ctr_synchronize(ctx) -> None:
     _check(ctx, _lib.ctr_synchronize(ctx))
 
@@ -412,6 +422,13 @@ def ctr_mc_stats(mc):
     return {"steps": v[0].value, "proposed": v[1].value, "lazy_rejected": v[2].value, "accepted": v[3].value}
 
 
+def ctr_mc_timing(mc):
+    """(host ms, trace ms) accumulated by ctr_mc_step."""
+    h, t = ctypes.c_double(), ctypes.c_double()
+    _check(None, _lib.ctr_mc_timing(mc, ctypes.byref(h), ctypes.byref(t)))
+    return h.value, t.value
+
+
 def ctr_mc_destroy(mc) -> None:
     _lib.ctr_mc_destroy(mc)
 
@@ -435,6 +452,9 @@ class MarkovChains:
 
     def stats(self):
         return ctr_mc_stats(self.mc)
+
+    def timing(self):
+        return ctr_mc_timing(self.mc)
 
     def close(self):
         if getattr(self, "mc", None):
