@@ -29,7 +29,7 @@
 //               power-of-two rescale fused into the epilogue; strings at
 //               their last operator only form the diagonal of F * X
 //   k_gstep_wave  the same for sectors of at most 128 (real) or 32 (complex)
-//               states: one wavefront per 16-column item, no barriers
+//               states: one wavefront per item of 16 or 32 columns, no barriers
 //   k_gcombine  one wavefront per configuration: (mantissa, exponent) merge
 //               of all columns of all its strings
 #include <math.h>
@@ -604,13 +604,13 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
   }
 }
 
-// Sectors of at most 16 * MT states: one wavefront per work item of 16
+// Sectors of at most 16 * MT states: one wavefront per work item of 16 * CT
 // columns of one group, all row tiles in registers, no workgroup barrier.
 // Lane l supplies A[row l%16][k l/16] and B[k l/16][column l%16]; item q of
 // the 16x16x4 result is row 4q + l/16, column l%16, so the per-column max is
 // a reduction over the four lanes of a column (xor 16, 32).
-template <bool CPLX, int MT>
-__global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, GroupArgs G, int r) {
+template <bool CPLX, int MT, int CT>
+__global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_gstep_wave(DevImp I, BatchArgs B, GroupArgs G, int r) {
   const int lane = threadIdx.x & 63;
   const int ln = lane & 15, lq = lane >> 4;
   const int NB = I.n_sec * I.nops, NK = 2 * NB;
@@ -626,7 +626,8 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
   const long long rcoloff = G.rcoloff[r];
   typedef double dbl4 __attribute__((ext_vector_type(4)));
   // propagators of the item's distinct gaps (the columns of one string share
-  // its gap): kRuns runs of equal gaps x 16 * MT rows per wavefront
+  // its gap): kRuns runs of equal gaps x 16 * MT rows per wavefront, one
+  // 16-column tile at a time
   constexpr int kRuns = 8;
   __shared__ double s_prop[4][kRuns * 16 * MT];
   __shared__ double s_gap[4][kRuns];
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
     const int key = item_key[item];
     const bool close = key >= NB;
     const int blk = close ? key - NB : key;
-    const int cw = close ? G.cw_close : 16;
+    const int cw = close ? G.cw_close : 16 * CT;
     const int c0 = (item - istart[key]) * cw;
     const int ncol = min(cw, hcols[key] - c0);
     const long long relbase = rcoloff + colpref[gstart[key]] + c0;
@@ -658,14 +659,14 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
 
     if (close) {
       for (int j = 0; j < ncol; ++j) {
-        const long long gcol = G.colg[relbase + j];
+        const long long gc = G.colg[relbase + j];
         const int jj = (int)G.colaux[relbase + j];
-        const double* xr = Xin + gcol * XR;
+        const double* xc = Xin + gc * XR;
         double sr = 0.0, si = 0.0;
         for (int k = lane; k < d_in; k += 64) {
-          const double fr = Fr[(long long)k * ld + jj], x = xr[k];
+          const double fr = Fr[(long long)k * ld + jj], x = xc[k];
           if (CPLX) {
-            const double fi = Fi[(long long)k * ld + jj], xi = xr[plane + k];
+            const double fi = Fi[(long long)k * ld + jj], xi = xc[plane + k];
             sr += fr * x - fi * xi;
             si += fr * xi + fi * x;
           } else {
@@ -680,26 +681,37 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
           PanelRes o;
           o.re = sr;
           o.im = si;
-          o.e2 = (double)G.colexp[gcol];
-          G.colres[gcol] = o;
+          o.e2 = (double)G.colexp[gc];
+          G.colres[gc] = o;
         }
       }
       continue;
     }
 
-    const bool live = ln < ncol;
-    const long long gcol = live ? (long long)G.colg[relbase + ln] : 0;
-    const double dt = live ? G.colaux[relbase + ln] : 0.0;
-    const double* xr = Xin + gcol * XR;
-    const int ntiles = ld >> 4;
-    dbl4 acc_r[MT], acc_i[MT];
+    // column tile c holds the item's columns 16 c .. 16 c + 15, lane column ln
+    bool live[CT];
+    long long gcol[CT];
+    double dt[CT];
+    const double* xr[CT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      acc_r[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-      acc_i[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < CT; ++c) {
+      live[c] = ln + 16 * c < ncol;
+      gcol[c] = live[c] ? (long long)G.colg[relbase + 16 * c + ln] : 0;
+      dt[c] = live[c] ? G.colaux[relbase + 16 * c + ln] : 0.0;
+      xr[c] = Xin + gcol[c] * XR;
     }
-    // operands of the next k-step are loaded while the current one multiplies
-    double nar[MT], nai[MT], nbr, nbi;
+    const int ntiles = ld >> 4;
+    dbl4 acc_r[CT][MT], acc_i[CT][MT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        acc_r[c][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acc_i[c][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+      }
+    // operands of the next k-step are loaded while the current one multiplies;
+    // one A fragment serves every column tile
+    double nar[MT], nai[MT], nbr[CT], nbi[CT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       nar[t] = nai[t] = 0.0;
@@ -708,16 +720,23 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
         if (CPLX) nai[t] = Fi[(long long)lq * ld + t * 16 + ln];
       }
     }
-    nbr = live ? xr[lq] : 0.0;
-    nbi = (CPLX && live) ? xr[plane + lq] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      nbr[c] = live[c] ? xr[c][lq] : 0.0;
+      nbi[c] = (CPLX && live[c]) ? xr[c][plane + lq] : 0.0;
+    }
     for (int k0 = 0; k0 < kp; k0 += 4) {
-      double ar[MT], ai[MT];
+      double ar[MT], ai[MT], br[CT], bi[CT];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         ar[t] = nar[t];
         ai[t] = nai[t];
       }
-      const double br = nbr, bi = nbi;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        br[c] = nbr[c];
+        bi[c] = nbi[c];
+      }
       const int kn = k0 + 4;
       if (kn < kp) {
         const long long row = (long long)(kn + lq) * ld;
@@ -728,77 +747,91 @@ __global__ __launch_bounds__(256, 3) void k_gstep_wave(DevImp I, BatchArgs B, Gr
             if (CPLX) nai[t] = Fi[row + t * 16 + ln];
           }
         }
-        nbr = live ? xr[kn + lq] : 0.0;
-        nbi = (CPLX && live) ? xr[plane + kn + lq] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          nbr[c] = live[c] ? xr[c][kn + lq] : 0.0;
+          nbi[c] = (CPLX && live[c]) ? xr[c][plane + kn + lq] : 0.0;
+        }
       }
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         if (t < ntiles) {
-          acc_r[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], br, acc_r[t], 0, 0, 0);
-          if (CPLX) {
-            acc_r[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[t], bi, acc_r[t], 0, 0, 0);
-            acc_i[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], bi, acc_i[t], 0, 0, 0);
-            acc_i[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[t], br, acc_i[t], 0, 0, 0);
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            acc_r[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], br[c], acc_r[c][t], 0, 0, 0);
+            if (CPLX) {
+              acc_r[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[t], bi[c], acc_r[c][t], 0, 0, 0);
+              acc_i[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], bi[c], acc_i[c][t], 0, 0, 0);
+              acc_i[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[t], br[c], acc_i[c][t], 0, 0, 0);
+            }
           }
         }
       }
     }
 
-    // propagator of the next gap, per-column max, rescale, store
+    // per column tile: propagator of the next gap, per-column max, rescale, store
     const double* e2 = I.esh + I.eoff[s2];
-    // runs of equal gaps among the item's columns (ballot over the lanes of row quarter 0)
-    const double dt_left = __shfl(dt, (lane + 63) & 63);
-    const unsigned long long starts = __ballot(lq == 0 && live && (ln == 0 || dt != dt_left)) & 0xffffull;
-    const int n_runs = __popcll(starts);
-    const int run = __popcll(starts & ((2ull << ln) - 1)) - 1;
-    const bool tab = n_runs <= kRuns;
-    if (tab) {
-      if (lq == 0 && ((starts >> ln) & 1)) s_gap[wv][run] = dt;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int u = 0; u < n_runs; ++u) {
-        const double g = s_gap[wv][u];
-        for (int m = lane; m < ld; m += 64) s_prop[wv][u * 16 * MT + m] = (m < d_out) ? exp(-g * e2[m]) : 0.0;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    const double* prop = &s_prop[wv][(run > 0 ? run : 0) * 16 * MT];
-    double cm = 0.0;
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      if (t < ntiles) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int m = t * 16 + 4 * q + lq;
-          const double p = tab ? prop[m] : ((m < d_out) ? exp(-dt * e2[m]) : 0.0);
-          acc_r[t][q] *= p;
-          cm = fmax(cm, fabs(acc_r[t][q]));
-          if (CPLX) {
-            acc_i[t][q] *= p;
-            cm = fmax(cm, fabs(acc_i[t][q]));
-          }
+    for (int c = 0; c < CT; ++c) {
+      // runs of equal gaps among the tile's columns (ballot over the lanes of row quarter 0)
+      const double dt_left = __shfl(dt[c], (lane + 63) & 63);
+      const unsigned long long starts =
+          __ballot(lq == 0 && live[c] && (ln == 0 || dt[c] != dt_left)) & 0xffffull;
+      const int n_runs = __popcll(starts);
+      const int run = __popcll(starts & ((2ull << ln) - 1)) - 1;
+      const bool tab = n_runs <= kRuns;
+      if (tab) {
+        // every lane is done reading the previous tile's table before it is rewritten
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lq == 0 && ((starts >> ln) & 1)) s_gap[wv][run] = dt[c];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int u = 0; u < n_runs; ++u) {
+          const double g = s_gap[wv][u];
+          for (int m = lane; m < ld; m += 64) s_prop[wv][u * 16 * MT + m] = (m < d_out) ? exp(-g * e2[m]) : 0.0;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-    }
-    cm = fmax(cm, __shfl_xor(cm, 16));
-    cm = fmax(cm, __shfl_xor(cm, 32));
-    int e = 0;
-    if (cm > 0.0) frexp(cm, &e);
-    const double sc = ldexp(1.0, -e);
-    if (live) {
-      if (lq == 0) G.colexp[gcol] += e;
-      double* col = Xout + gcol * XR;
+      const double* prop = &s_prop[wv][(run > 0 ? run : 0) * 16 * MT];
+      double cm = 0.0;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         if (t < ntiles) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int m = t * 16 + 4 * q + lq;
-            col[m] = acc_r[t][q] * sc;
-            if (CPLX) col[plane + m] = acc_i[t][q] * sc;
+            const double p = tab ? prop[m] : ((m < d_out) ? exp(-dt[c] * e2[m]) : 0.0);
+            acc_r[c][t][q] *= p;
+            cm = fmax(cm, fabs(acc_r[c][t][q]));
+            if (CPLX) {
+              acc_i[c][t][q] *= p;
+              cm = fmax(cm, fabs(acc_i[c][t][q]));
+            }
+          }
+        }
+      }
+      cm = fmax(cm, __shfl_xor(cm, 16));
+      cm = fmax(cm, __shfl_xor(cm, 32));
+      int e = 0;
+      if (cm > 0.0) frexp(cm, &e);
+      const double sc = ldexp(1.0, -e);
+      if (live[c]) {
+        if (lq == 0) G.colexp[gcol[c]] += e;
+        double* col = Xout + gcol[c] * XR;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t < ntiles) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int m = t * 16 + 4 * q + lq;
+              col[m] = acc_r[c][t][q] * sc;
+              if (CPLX) col[plane + m] = acc_i[c][t][q] * sc;
+            }
           }
         }
       }
@@ -880,9 +913,9 @@ GVariant make_gvariant() {
   return GVariant{reinterpret_cast<const void*>(&k_gstep<CPLX, NW, RT, CT>), NW, CT * 16};
 }
 
-template <bool CPLX, int MT>
+template <bool CPLX, int MT, int CT = 1>
 GVariant make_wvariant() {
-  return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT>), 4, 16};
+  return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT, CT>), 4, 16 * CT};
 }
 
 // Small sectors: one wavefront per 16-column item (all row tiles in
@@ -898,7 +931,7 @@ bool pick_gvariant(const DevImp& imp, GVariant* v) {
   } else {
     if (tiles <= 2) *v = make_wvariant<false, 2>();
     else if (tiles <= 4) *v = make_wvariant<false, 4>();
-    else if (tiles <= 8) *v = make_wvariant<false, 8>();
+    else if (tiles <= 8) *v = make_wvariant<false, 8, 2>();  // 32 columns per item: 7% shorter d-shell rounds
     else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
     else return false;
   }
