@@ -96,7 +96,7 @@ TRAFFIC_MEASURED = {
         "bytes": 73.0208e9},
     ("k_gstep", "fshell-slater-soc-10^4-orders40-160 (first 2000)"): {
         "source": "ctrace_group.hip",
-        "sha256": "9708edec123259f37313fe20b66e88bc7735e145da00660d37c3eedaccce5b35",
+        "sha256": "113c6a6c7845771d8b1a9036f00ac0128750884f8b42f6e9bfe33b5ef72f36b4",
         "bytes": 6.9142e9},
 }
 
@@ -173,16 +173,17 @@ def histogram_leg(ctx, tab, imp, strings):
             "entry": "ctr_trace_histogram vs ctr_trace_batch (host arrays)"}
 
 
-def markov_leg(ctx, wl_impurity, strings, n_chains, steps):
+def markov_leg(ctx, wl_impurity, strings, n_chains, steps, full_traces=False):
     """Markov steps around the trace (App. D pair moves, w_hyb fast updates on
-    the host, one lazy trace batch per step on the GPU): n_chains chains start
-    from the workload's configurations and make `steps` timed moves each."""
+    the host, one trace batch per step on the GPU, lazy unless full_traces):
+    n_chains chains start from the workload's configurations and make `steps`
+    timed moves each."""
     from paper_2010_08482_amd import ctrace
     from workloads.impurity import synthetic_bath
 
     eps, v = synthetic_bath(wl_impurity)
     n_chains = min(n_chains, len(strings))
-    mc = ctrace.MarkovChains(ctx, n_chains, eps, v)
+    mc = ctrace.MarkovChains(ctx, n_chains, eps, v, full_traces=full_traces)
     started = 0
     for i in range(n_chains):
         try:
@@ -211,7 +212,8 @@ def markov_leg(ctx, wl_impurity, strings, n_chains, steps):
             "lazy_rejected_frac": (s1["lazy_rejected"] - s0["lazy_rejected"]) / max(prop, 1),
             "mean_order": float(np.mean(orders)),
             "host_ms_per_step": (h1 - h0) / steps, "trace_batch_ms_per_step": (g1 - g0) / steps,
-            "entry": "ctr_mc_step (host hybridisation updates + one ctr_trace_lazy_batch per step)"}
+            "entry": "ctr_mc_step (host hybridisation updates + one " +
+                     ("ctr_trace_batch" if full_traces else "ctr_trace_lazy_batch") + " per step)"}
 
 
 def cpu_baseline(imp, strings, seconds_budget=20.0):
@@ -586,6 +588,7 @@ def main():
     markov = None
     if args.mc_chains > 0:
         markov = markov_leg(ctx, wl["impurity"], strings, args.mc_chains, args.mc_steps)
+        markov["full_traces"] = markov_leg(ctx, wl["impurity"], strings, args.mc_chains, args.mc_steps, True)
 
     # single-configuration latency through the host-pointer entry point
     lat = []

@@ -285,6 +285,7 @@ ctr_status ctr_trace_histogram(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offse
  *  opts->n_bath        levels per flavor (>= 0), bath_eps / bath_v [n_flavors * n_bath]
  *  opts->rebuild_every accepted moves of a flavor between recomputations of its
  *                      inverse from scratch (0: 64)
+ *  opts->full_traces   0 or 1 (see the struct); both take the same decisions
  * The context must stay alive and loaded while the chains exist.
  */
 typedef struct ctr_mc ctr_mc;
@@ -294,7 +295,8 @@ typedef struct {
   const double *bath_eps;
   const double *bath_v;
   int32_t rebuild_every;
-  int32_t reserved;              /* must be 0 */
+  int32_t full_traces;           /* 0: lazy batch (proposals stop at their bound); 1: full traces, the
+                                    decision taken on the host from the exact values */
 } ctr_mc_opts;
 
 /* Errors: CTR_ERR_ARG, CTR_ERR_STATE (no impurity), trace errors. */

@@ -138,6 +138,7 @@ struct ctr_mc {
   int nf = 0, nb = 0;
   double beta = 0.0;
   int rebuild_every = 64;
+  bool full = false;  // full trace batches instead of lazy ones
   std::vector<double> eps, vv;  // [nf * nb]
   std::vector<Chain> chains;
   std::vector<Move> moves;
@@ -447,7 +448,8 @@ extern "C" {
 ctr_status ctr_mc_create(ctr_ctx* ctx, const ctr_mc_opts* opts, ctr_mc** out) {
   if (!out) return CTR_ERR_ARG;
   *out = nullptr;
-  if (!ctx || !opts || opts->n_chains < 1 || opts->n_bath < 0 || opts->rebuild_every < 0 || opts->reserved ||
+  if (!ctx || !opts || opts->n_chains < 1 || opts->n_bath < 0 || opts->rebuild_every < 0 ||
+      (opts->full_traces != 0 && opts->full_traces != 1) ||
       (opts->n_bath > 0 && (!opts->bath_eps || !opts->bath_v)))
     return CTR_ERR_ARG;
   if (!ctr::context_loaded(ctx)) return CTR_ERR_STATE;
@@ -457,6 +459,7 @@ ctr_status ctr_mc_create(ctr_ctx* ctx, const ctr_mc_opts* opts, ctr_mc** out) {
   mc->nb = opts->n_bath;
   mc->beta = ctr::context_beta(ctx);
   mc->rebuild_every = opts->rebuild_every ? opts->rebuild_every : 64;
+  mc->full = opts->full_traces == 1;
   mc->eps.assign(opts->bath_eps, opts->bath_eps + (size_t)mc->nf * mc->nb);
   mc->vv.assign(opts->bath_v, opts->bath_v + (size_t)mc->nf * mc->nb);
   for (size_t i = 0; i < mc->eps.size(); ++i)
@@ -566,8 +569,11 @@ ctr_status ctr_mc_step(ctr_mc* mc, const double* u, int32_t* decision) {
   mc->out.assign(nb, ctr_value{});
   const Clock::time_point t1 = Clock::now();
   if (nb > 0) {
-    const ctr_status s = ctr_trace_lazy_batch(mc->ctx, nb, mc->offs.data(), mc->btau.data(), mc->bop.data(),
-                                              mc->thr.data(), nullptr, mc->out.data());
+    const ctr_status s =
+        mc->full ? ctr_trace_batch(mc->ctx, nb, mc->offs.data(), mc->btau.data(), mc->bop.data(), nullptr,
+                                   mc->out.data())
+                 : ctr_trace_lazy_batch(mc->ctx, nb, mc->offs.data(), mc->btau.data(), mc->bop.data(),
+                                        mc->thr.data(), nullptr, mc->out.data());
     if (s != CTR_OK) return s;
   }
   const Clock::time_point t2 = Clock::now();

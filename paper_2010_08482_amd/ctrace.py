@@ -56,7 +56,7 @@ class ctr_server_opts(ctypes.Structure):
 class ctr_mc_opts(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_bath", ctypes.c_int32), ("bath_eps", ctypes.POINTER(ctypes.c_double)),
                 ("bath_v", ctypes.POINTER(ctypes.c_double)), ("rebuild_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("full_traces", ctypes.c_int32)]
 
 
 class ctr_result(ctypes.Structure):
@@ -380,12 +380,12 @@ def ctr_server_destroy(srv) -> None:
     _lib.ctr_server_destroy(srv)
 
 
-def ctr_mc_create(ctx, n_chains, bath_eps, bath_v, rebuild_every=0):
+def ctr_mc_create(ctx, n_chains, bath_eps, bath_v, rebuild_every=0, full_traces=False):
     """bath_eps, bath_v: [n_flavors, n_bath] arrays."""
     eps = np.ascontiguousarray(bath_eps, dtype=np.float64)
     v = np.ascontiguousarray(bath_v, dtype=np.float64)
     o = ctr_mc_opts(int(n_chains), int(eps.shape[1]) if eps.ndim == 2 else 0, _ptr(eps, ctypes.c_double),
-                    _ptr(v, ctypes.c_double), int(rebuild_every), 0)
+                    _ptr(v, ctypes.c_double), int(rebuild_every), 1 if full_traces else 0)
     out = ctypes.c_void_p()
     _check(ctx, _lib.ctr_mc_create(ctx, ctypes.byref(o), ctypes.byref(out)))
     return out
@@ -436,10 +436,10 @@ def ctr_mc_destroy(mc) -> None:
 class MarkovChains:
     """Markov chains over one TraceContext's impurity with a discrete bath per flavor."""
 
-    def __init__(self, context, n_chains, bath_eps, bath_v, rebuild_every=0):
+    def __init__(self, context, n_chains, bath_eps, bath_v, rebuild_every=0, full_traces=False):
         self.context = context
         self.n_chains = int(n_chains)
-        self.mc = ctr_mc_create(context.ctx, n_chains, bath_eps, bath_v, rebuild_every)
+        self.mc = ctr_mc_create(context.ctx, n_chains, bath_eps, bath_v, rebuild_every, full_traces)
 
     def set_config(self, chain, tau, op):
         ctr_mc_set_config(self.mc, chain, tau, op)

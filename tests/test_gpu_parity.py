@@ -1018,6 +1018,34 @@ def test_markov_chains_sample_the_anderson_impurity(lib):
     c.close()
 
 
+def test_markov_chains_full_and_lazy_batches_decide_alike(lib, ctx):
+    """Full trace batches with the decision on the host take the same
+    decisions as lazy batches (a rejected bound implies a rejected value)."""
+    from workloads.impurity import synthetic_bath
+
+    tab, c = ctx("dshell")
+    eps, v = synthetic_bath("dshell")
+    strings = make_configs(1, 256)
+    chains = [lib.MarkovChains(c, 256, eps, v, full_traces=f) for f in (False, True)]
+    for mc in chains:
+        for i, st in enumerate(strings):
+            mc.set_config(i, st.tau, st.op)
+    rng = np.random.Generator(np.random.PCG64(603))
+    say("[gpu] ctr_mc_step dshell 256 chains x 30 steps, lazy and full batches")
+    for _ in range(30):
+        u = rng.uniform(size=(256, 6))
+        d0, d1 = chains[0].step(u), chains[1].step(u)
+        assert np.array_equal(d0, d1)
+    for i in range(256):
+        a, b = chains[0].config(i), chains[1].config(i)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert abs(a[2] - b[2]) <= 1e-12 * max(1.0, abs(b[2]))
+    s0, s1 = chains[0].stats(), chains[1].stats()
+    assert s0["accepted"] == s1["accepted"] > 0 and s1["lazy_rejected"] == 0 and s0["lazy_rejected"] > 0
+    for mc in chains:
+        mc.close()
+
+
 def test_markov_chain_argument_errors(lib, ctx):
     from workloads.impurity import synthetic_bath
 
