@@ -600,6 +600,7 @@ def main():
 
     cpu = None
     rel = None
+    rel_dist = None
     block_sparse = None
     if not args.no_cpu:
         sample = strings[: args.cpu_sample]
@@ -617,6 +618,8 @@ def main():
             b = complex(ref[0]) * math.exp(ref[1] - M)
             errs.append(abs(a - b) / abs(b))
         rel = max(errs) if errs else None
+        rel_dist = {"p50": float(np.percentile(errs, 50)), "p99": float(np.percentile(errs, 99)),
+                    "max": float(max(errs)), "n": len(errs)} if errs else None
         block_sparse = cpu_block_sparse(tab, strings)
 
     value = n_cfg * args.steps / elapsed
@@ -654,6 +657,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "entry": "ctr_trace (one configuration, host pointers)"},
         "max_rel_err_vs_oracle_sample": rel,
+        "rel_err_vs_oracle_sample": rel_dist,
         "fp32_split": split,
         "lazy": lazy,
         "histogram": hist,
