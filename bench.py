@@ -235,6 +235,34 @@ def cpu_baseline(imp, strings, seconds_budget=20.0):
     return len(done) / el, len(done), el, threads, done
 
 
+def cpu_oracle_extrapolated(tab, strings, probe_dim=1024):
+    """The dense CPU oracle's cost on a full-size impurity, extrapolated: it
+    multiplies one 2^n x 2^n matrix per operator, so a trace costs the mean
+    operator count times one such product, timed here at probe_dim and scaled
+    by (2^n / probe_dim)^3.  Labelled as extrapolated."""
+    from threadpoolctl import threadpool_info
+
+    D = 1 << tab.n_flavors
+    dtype = np.complex128 if tab.is_complex else np.float64
+    rng = np.random.Generator(np.random.PCG64(5))
+    a = rng.standard_normal((probe_dim, probe_dim)).astype(dtype)
+    b = rng.standard_normal((probe_dim, probe_dim)).astype(dtype)
+    a @ b  # warm
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        a @ b
+    t_probe = (time.perf_counter() - t0) / reps
+    t_product = t_probe * (D / probe_dim) ** 3
+    mean_ops = float(np.mean([s.n for s in strings]))
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") in
+                   ("openblas", "mkl", "blis")] or [1])
+    return {"value": 1.0 / (t_product * mean_ops), "unit": "trace evals/s", "cores": threads,
+            "kind": "oracle (extrapolated)",
+            "sample": f"one {probe_dim}^3 {'complex' if tab.is_complex else 'real'} product in {t_probe * 1e3:.1f} ms, "
+                      f"x ({D}/{probe_dim})^3 per operator, {mean_ops:.0f} operators per trace"}
+
+
 def cpu_block_sparse(tab, strings, seconds_budget=5.0):
     """The same sector-block algorithm (walk, block products, trace) in NumPy
     FP64 on the host (the tests' block reference), on a bounded sample: with
@@ -391,7 +419,6 @@ def fp64_throughput(wl_id, n_configs, steps, warmup):
     print(f"[bench] also: {name}", file=sys.stderr, flush=True)
     free, _ = torch.cuda.mem_get_info(0)
     ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
-    peaks = ctrace.ctr_probe_peaks(ctx.ctx)
     offs, tau, op = pack(strings)
     dev = "cuda:0"
     d_offs, d_tau, d_op = (torch.from_numpy(a).to(dev) for a in (offs, tau, op))
@@ -419,7 +446,9 @@ def fp64_throughput(wl_id, n_configs, steps, warmup):
     lps = launches / max(steps, 1)
     achieved = flops / lps / (per_launch * 1e-3) / 1e12 if per_launch > 0 else None
     kname = chain_kernel_name(tab, n_cfg)
+    cpu = cpu_oracle_extrapolated(tab, strings)
     return name, {"value": n_cfg * steps / elapsed, "unit": "trace evals/s", "steps": steps, "warmup": warmup,
+                  "cpu_baseline_extrapolated": cpu,
                   "ms_per_step": elapsed / steps * 1e3, "dtype": "c128" if tab.is_complex else "f64",
                   "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                "frac": achieved / PEAK_FP64_TFLOPS if achieved else None,
