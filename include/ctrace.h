@@ -82,10 +82,12 @@ typedef struct {
 
 /* ctr_opts.kernel: which chain kernel runs the block products */
 enum {
-  CTR_KERNEL_AUTO = 0,    /* FP64 with sectors <= 128 states: the wavefront kernel; else, for
-                             batches of >= 256 non-lazy FP64 traces, the block-grouped rounds when
-                             the sectors fit them and the arena holds their scratch; else the
-                             LDS-resident workgroup kernel when the panel fits LDS, else streaming */
+  CTR_KERNEL_AUTO = 0,    /* the kernel ctr_tune picked, for non-lazy FP64 batches of at least a
+                             quarter of its sample; otherwise FP64 with sectors <= 128 states: the
+                             wavefront kernel; else, for batches of >= 256 FP64 traces (lazy ones
+                             included), the block-grouped rounds when the sectors fit them and the
+                             arena holds their scratch; else the LDS-resident workgroup kernel when
+                             the panel fits LDS, else streaming */
   CTR_KERNEL_WAVE = 1,    /* one wavefront per 8-column panel; sectors <= 128 states, FP64 only */
   CTR_KERNEL_BLOCK = 2,   /* one workgroup per 16-column panel, X in LDS (<= 1024 real / 576 complex) */
   CTR_KERNEL_STREAM = 3,  /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
