@@ -339,16 +339,20 @@ ctr_status ctr_bound(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32
 ctr_status ctr_strings(ctr_ctx *ctx, int32_t n_ops, const int32_t *op, int32_t *q0_out, int32_t *n_out);
 
 /*
- * Autotuning of the chain kernel (the tile shapes differ: 8-column panels on
+ * Autotuning of the chain kernel and its tile shape (8-column panels on
  * 4x4x4 MFMA, 16-column panels on 16x16x4, grouped items of 16/32/64
- * columns).  Evaluates the sample batch (host arrays, as ctr_trace_batch)
- * once with every kernel that can run it in FP64, timing each second run with
- * HIP events, and makes the fastest the choice of CTR_KERNEL_AUTO for FP64
- * batches of at least n_cfg / 4 traces (smaller batches and lazy or
+ * columns; the grouped rounds in each of their tile shapes for this
+ * impurity).  Evaluates the sample batch (host arrays, as ctr_trace_batch)
+ * once with every kernel and shape that can run it in FP64, timing each second
+ * run with HIP events.  The grouped rounds keep their fastest shape (for
+ * every later call that runs them), and the fastest kernel becomes the
+ * choice of CTR_KERNEL_AUTO for FP64 batches of at least n_cfg / 4 traces
+ * (smaller batches and lazy or
  * FP32-split calls keep the built-in choice) until the next
  * ctr_set_impurity.  *chosen (may be NULL) receives the CTR_KERNEL_* picked;
  * ms_per_kernel (may be NULL) receives 5 entries indexed by CTR_KERNEL_*,
- * the measured milliseconds or -1 where a kernel did not run.
+ * the measured milliseconds (the best shape's for the grouped rounds) or -1
+ * where a kernel did not run.
  */
 ctr_status ctr_tune(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau, const int32_t *op,
                     int32_t *chosen, double *ms_per_kernel);

@@ -918,31 +918,32 @@ GVariant make_wvariant() {
   return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT, CT>), 4, 16 * CT};
 }
 
-// Small sectors: one wavefront per 16-column item (all row tiles in
-// registers); larger ones: a workgroup per 32/64-column item, rows split
-// over its wavefronts.
-bool pick_gvariant(const DevImp& imp, GVariant* v) {
+// Small sectors: one wavefront per item of 16 or 32 columns (all row tiles
+// in registers); larger ones: a workgroup per 32/64-column item, rows split
+// over its wavefronts.  alt = 1 selects the other measured tile shape where
+// there is one (the autotuner times both); false if there is none.
+bool pick_gvariant(const DevImp& imp, int alt, GVariant* v) {
   const int tiles = imp.xrows / 16;
   if (imp.is_complex) {
     if (tiles <= 2) *v = make_wvariant<true, 2>();
     else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
-    else if (tiles <= 24) *v = make_gvariant<true, 12, 2, 2>();  // 12 waves x 2 row tiles: 3 waves per SIMD
+    else if (tiles <= 24) *v = alt ? make_gvariant<true, 8, 3, 2>() : make_gvariant<true, 12, 2, 2>();
     else return false;
-  } else {
-    if (tiles <= 2) *v = make_wvariant<false, 2>();
-    else if (tiles <= 4) *v = make_wvariant<false, 4>();
-    else if (tiles <= 8) *v = make_wvariant<false, 8, 2>();  // 32 columns per item: 7% shorter d-shell rounds
-    else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
-    else return false;
+    return !alt || (tiles > 8 && tiles <= 24);
   }
-  return true;
+  if (tiles <= 2) *v = make_wvariant<false, 2>();
+  else if (tiles <= 4) *v = make_wvariant<false, 4>();
+  else if (tiles <= 8) *v = alt ? make_wvariant<false, 8, 1>() : make_wvariant<false, 8, 2>();
+  else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
+  else return false;
+  return !alt || (tiles > 4 && tiles <= 8);
 }
 
 }  // namespace
 
-int group_grid(const DevImp& imp, int device, int* cw_step) {
+int group_grid(const DevImp& imp, int device, int alt, int* cw_step) {
   GVariant v;
-  if (!pick_gvariant(imp, &v)) return 0;
+  if (!pick_gvariant(imp, alt, &v)) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.nw * 64, 0) != hipSuccess) return 0;
   int cus = 0;
@@ -982,10 +983,11 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
   return hipGetLastError();
 }
 
-hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
+hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
                               hipStream_t stream) {
   GVariant v;
-  if (!pick_gvariant(imp, &v) || grid <= 0) return hipErrorInvalidValue;
+  if (!pick_gvariant(imp, alt, &v) || grid <= 0) return hipErrorInvalidValue;
+  if (v.cw != g.cw_step) return hipErrorInvalidValue;  // the schedule was built for another item width
   void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b), const_cast<GroupArgs*>(&g), &r};
   return hipLaunchKernel(v.fn, dim3(grid), dim3(v.nw * 64), args, 0, stream);
 }

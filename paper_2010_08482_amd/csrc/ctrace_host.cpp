@@ -38,6 +38,7 @@ struct ctr_ctx {
   int grid_big = 0;   // streaming kernel
   int grid_group = 0;  // block-grouped rounds, 0 = not applicable
   int cw_group = 0;    // columns per grouped work item
+  int galt = 0;        // grouped tile shape: 0 default, 1 the alternative (picked by ctr_tune)
   int tuned = 0;       // CTR_KERNEL_* picked by ctr_tune for FP64 batches (0 = none)
   int tuned_min_batch = 0;
   double* xbuf = nullptr;  // the streaming kernel's per-workgroup X buffers
@@ -199,7 +200,7 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
       HIP_TRY(ctx, hipEventCreate(&t1));
       HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
     }
-    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, ctx->grid_group, ctx->stream)) != hipSuccess)
+    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, ctx->grid_group, ctx->galt, ctx->stream)) != hipSuccess)
       return hip_fail(ctx, e, "grouped round kernel");
     if (ctx->timing) {
       HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
@@ -699,7 +700,8 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
   ctx->cw_group = 0;
-  ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, &ctx->cw_group);
+  ctx->galt = 0;
+  ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, 0, &ctx->cw_group);
   ctx->tuned = 0;
   ctx->tuned_min_batch = 0;
   ctx->xbuf = nullptr;
@@ -734,10 +736,35 @@ ctr_status ctr_tune(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const d
     for (int k = 0; k < 5; ++k) ms_per_kernel[k] = -1.0;
   ctx->tuned = 0;
   std::vector<ctr_value> out(n_cfg);
-  const int cands[4] = {CTR_KERNEL_WAVE, CTR_KERNEL_BLOCK, CTR_KERNEL_STREAM, CTR_KERNEL_GROUPED};
-  int best = 0;
-  double best_ms = 0.0;
-  for (int want : cands) {
+  // candidates: every kernel, the grouped rounds in each of their tile shapes
+  const int cands[5][2] = {{CTR_KERNEL_WAVE, 0}, {CTR_KERNEL_BLOCK, 0}, {CTR_KERNEL_STREAM, 0},
+                           {CTR_KERNEL_GROUPED, 0}, {CTR_KERNEL_GROUPED, 1}};
+  int best = 0, g_alt = 0;
+  double best_ms = 0.0, g_ms = -1.0;
+  const int grid0 = ctx->grid_group, cw0 = ctx->cw_group;
+  // an error return leaves the grouped rounds in their default tile shape
+  struct Restore {
+    ctr_ctx* c;
+    int grid, cw;
+    bool keep = false;
+    ~Restore() {
+      if (!keep) {
+        c->galt = 0;
+        c->grid_group = grid;
+        c->cw_group = cw;
+      }
+    }
+  } restore{ctx, grid0, cw0};
+  for (const auto& cand : cands) {
+    const int want = cand[0], alt = cand[1];
+    if (want == CTR_KERNEL_GROUPED) {
+      int cw = 0;
+      const int grid = ctr::group_grid(ctx->imp, ctx->device, alt, &cw);
+      if (grid <= 0) continue;
+      ctx->galt = alt;
+      ctx->grid_group = grid;
+      ctx->cw_group = cw;
+    }
     ctr_opts o{};
     o.kernel = want;
     bool split = false;
@@ -760,12 +787,21 @@ ctr_status ctr_tune(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const d
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (s != CTR_OK) return s;
-    if (ms_per_kernel) ms_per_kernel[want] = ms;
+    if (ms_per_kernel && (ms_per_kernel[want] < 0.0 || ms < ms_per_kernel[want])) ms_per_kernel[want] = ms;
+    if (want == CTR_KERNEL_GROUPED && (g_ms < 0.0 || ms < g_ms)) {
+      g_alt = alt;
+      g_ms = ms;
+    }
     if (!best || ms < best_ms) {
       best = want;
       best_ms = ms;
     }
   }
+  // the grouped rounds keep their fastest tile shape
+  ctx->galt = g_alt;
+  ctx->grid_group = ctx->galt ? ctr::group_grid(ctx->imp, ctx->device, 1, &ctx->cw_group) : grid0;
+  if (!ctx->galt) ctx->cw_group = cw0;
+  restore.keep = true;
   ctx->err.clear();
   if (!best) return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel ran the sample");
   ctx->tuned = best;

@@ -162,11 +162,12 @@ int big_grid(const DevImp& imp, int device, size_t* lds_bytes);
 size_t big_xbuf_doubles(const DevImp& imp, int grid);
 hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf, int grid, hipStream_t stream);
 // Block-grouped path (sectors of at most 384 states); grid 0 = not applicable.
-int group_grid(const DevImp& imp, int device, int* cw_step);
+// alt = 1: the alternative tile shape (grid 0 when there is none for this impurity).
+int group_grid(const DevImp& imp, int device, int alt, int* cw_step);
 hipError_t launch_group_prepare(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, long long max_strings,
                                 hipStream_t stream);
 hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
-hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid,
+hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
                               hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
 // Peak-rate probe (ctrace_probe.hip): out[0..4] = FP64 16x16x4 and 4x4x4 MFMA and FP32 16x16x4

@@ -776,6 +776,40 @@ def test_autotuner_picks_a_kernel_that_then_runs_under_auto(lib, ctx):
         a = c.trace_batch(small)
         w = c.trace_batch(small, kernel=lib.CTR_KERNEL_WAVE)
         assert np.array_equal(a["re"], w["re"])
+        # the grouped rounds in the tile shape the tuner kept agree with the per-string kernel
+        g = c.trace_packed(offs, tau, op, kernel=lib.CTR_KERNEL_GROUPED)
+        wv = c.trace_packed(offs, tau, op, kernel=lib.CTR_KERNEL_WAVE)
+        for x, y in zip(g, wv):
+            if y["re"] != 0:
+                assert rel_err(pair(x), pair(y)) < 1e-10 * max(1.0, math.exp(y["log_abs"] - y["log_scale"]
+                                                                            - math.log(abs(y["re"]))))
+    finally:
+        c.close()
+
+
+def test_autotuner_times_both_grouped_tile_shapes_fshell(lib, ctx):
+    """On the f-shell the grouped rounds have two tile shapes (12 x 2 and 8 x 3
+    wavefronts x row tiles); after tuning, whichever was kept gives the same
+    traces as the per-string kernel."""
+    tab, shared = ctx("fshell")
+    c = lib.TraceContext(tab)
+    try:
+        cfgs = make_configs(2, 300)
+        offs, tau, op = pack(cfgs)
+        say("[gpu] autotune fshell x300")
+        chosen, ms = c.tune(offs, tau, op)
+        say(f"autotune fshell: chose {chosen}, ms {ms}")
+        assert 4 in ms
+        g = c.trace_packed(offs, tau, op, kernel=lib.CTR_KERNEL_GROUPED)
+        b = c.trace_packed(offs, tau, op, kernel=lib.CTR_KERNEL_BLOCK)
+        n = 0
+        for x, y in zip(g, b):
+            if y["re"] == 0 and y["im"] == 0:
+                continue
+            n += 1
+            ratio = max(1.0, math.exp(y["log_abs"] - y["log_scale"] - math.log(abs(complex(y["re"], y["im"])))))
+            assert rel_err(pair(x), pair(y)) < 1e-10 * ratio
+        assert n > 100
     finally:
         c.close()
 
