@@ -24,6 +24,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+# The paper's own acceleration figures (abstract and Sec. 4): whole CT-HYB runs of
+# delta-Pu at 600 K, one NVIDIA Volta GPU with one CPU against one CPU, FP64.
+# Reported beside the measurement as context only: another machine and another
+# quantity (end-to-end solver time, not trace evaluations).
+PAPER_CONTEXT = {
+    "ctqmc_speedup_with_crystal_field": ">600x",
+    "ctqmc_speedup_without_crystal_field": ">100x",
+    "hardware": "Summit: 1 NVIDIA Volta GPU + 1 CPU vs 1 CPU",
+    "precision": "FP64",
+    "quantity": "whole CT-HYB solver, delta-Pu at 600 K (not trace evals/s)",
+    "use": "context only",
+}
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
@@ -691,6 +703,7 @@ def main():
         "lazy": lazy,
         "histogram": hist,
         "markov": markov,
+        "paper_context": PAPER_CONTEXT,
     }
     ctx.close()
     if not args.no_also and args.workload == 1:
