@@ -320,17 +320,19 @@ def serve_main(args):
     from workloads.configs import insert_pair, random_string, remove_pair
 
     names = ["dshell", "fshell"] + (["fshell_cf"] if args.serve_cf else [])
-    share = [0.75, 0.25] if not args.serve_cf else [0.625, 0.25, 0.125]
+    chain_share = [0.75, 0.25] if not args.serve_cf else [0.625, 0.25, 0.125]
     imps = [make_impurity(n) for n in names]
     free, _ = torch.cuda.mem_get_info(0)
     ctxs = []
     for imp in imps:
         tab = build_sectors(imp)
         print(f"[serve] {imp.name}: {tab.n_sectors} sectors, largest block {tab.max_dim}", file=sys.stderr, flush=True)
-        ctxs.append(ctrace.TraceContext(tab, scratch_bytes=int(min(free // (4 * len(imps)), 16 << 30))))
+        # a stream per impurity, so that the lanes' passes overlap on the device
+        ctxs.append(ctrace.TraceContext(tab, scratch_bytes=int(min(free // (4 * len(imps)), 16 << 30)),
+                                        stream=torch.cuda.Stream()))
     rng = np.random.Generator(np.random.PCG64(2024))
     n_chains = 256
-    kind = rng.choice(len(names), size=n_chains, p=share)
+    kind = rng.choice(len(names), size=n_chains, p=chain_share)
     chains = []
     for c in range(n_chains):
         imp = imps[kind[c]]
@@ -349,7 +351,8 @@ def serve_main(args):
             s = remove_pair(rng, s, imp.n_flavors)
         chains[c] = s
         reqs.append((int(kind[c]), s))
-    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch)
+    share = [float(x) for x in args.serve_grid_share.split(",")] if args.serve_grid_share else None
+    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch, grid_share=share)
     results = []
     done = threading.Event()
 
@@ -405,7 +408,8 @@ def serve_main(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "serving mix: 256 chains, Poisson arrivals, pair insert/remove moves",
-                   "impurities": names, "chain_share": share, "max_batch": args.serve_batch},
+                   "impurities": names, "chain_share": chain_share, "max_batch": args.serve_batch,
+                   "grid_share": share, "streams": "one per impurity"},
     }
     for c in ctxs:
         c.close()
@@ -498,6 +502,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="serving mix: seconds of arrivals")
     ap.add_argument("--serve-batch", type=int, default=4096, help="serving mix: most requests per device pass")
+    ap.add_argument("--serve-grid-share", default="",
+                    help="serving mix: per-impurity fractions of the persistent grids, e.g. 1,0.5 (default: full grids)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run here has a single MI355X and the trace path has no "

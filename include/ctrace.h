@@ -406,6 +406,12 @@ typedef struct {
                            ctr_server_submit returns CTR_ERR_BUSY beyond it */
   size_t hbm_budget;    /* per-call scratch bytes a batch may occupy in its context's arena;
                            0 = all of the arena not held by the impurity */
+  const double *grid_share; /* optional [n_ctx] fractions in (0, 1]: each context launches only that
+                           share of the workgroups of its persistent kernels while the server holds
+                           it (grouped rounds keep at least 64), so that a long pass of one impurity
+                           leaves slots on the device for the others' kernels; the contexts get the
+                           whole device back at ctr_server_destroy.  NULL: every context launches
+                           full grids */
 } ctr_server_opts;
 
 typedef struct {
@@ -420,8 +426,8 @@ typedef struct {
 
 /*
  * Starts one worker thread per context.  ctxs[n_ctx] must each have an
- * impurity loaded.  Errors: CTR_ERR_ARG (bad options or contexts),
- * CTR_ERR_STATE (a context without impurity).
+ * impurity loaded.  Errors: CTR_ERR_ARG (bad options or contexts, a grid
+ * share outside (0, 1]), CTR_ERR_STATE (a context without impurity).
  */
 ctr_status ctr_server_create(ctr_ctx *const *ctxs, int32_t n_ctx, const ctr_server_opts *opts,
                              ctr_server **out);

@@ -41,6 +41,7 @@ struct ctr_ctx {
   int galt = 0;        // grouped tile shape: 0 default, 1 the alternative (picked by ctr_tune)
   int tuned = 0;       // CTR_KERNEL_* picked by ctr_tune for FP64 batches (0 = none)
   int tuned_min_batch = 0;
+  double grid_share = 1.0;  // fraction of each persistent grid launched (a serving lane's share)
   double* xbuf = nullptr;  // the streaming kernel's per-workgroup X buffers
   unsigned int* counter = nullptr;
   bool timing = false;
@@ -56,6 +57,14 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 ctr_status fail(ctr_ctx* ctx, ctr_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
   return s;
+}
+
+// Workgroups of a persistent launch under the context's grid share: at least
+// `floor` (the kernel's own minimum, at most g), at most the full grid g.
+int shared_grid(const ctr_ctx* ctx, int g, int floor) {
+  if (g <= 0 || ctx->grid_share >= 1.0) return g;
+  const int n = (int)std::ceil(g * ctx->grid_share);
+  return std::min(g, std::max(std::min(g, floor), n));
 }
 
 ctr_status hip_fail(ctr_ctx* ctx, hipError_t e, const char* what) {
@@ -200,7 +209,8 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
       HIP_TRY(ctx, hipEventCreate(&t1));
       HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
     }
-    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, ctx->grid_group, ctx->galt, ctx->stream)) != hipSuccess)
+    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, shared_grid(ctx, ctx->grid_group, ctr::kGroupCounters), ctx->galt,
+                                       ctx->stream)) != hipSuccess)
       return hip_fail(ctx, e, "grouped round kernel");
     if (ctx->timing) {
       HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
@@ -234,12 +244,15 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
     HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
   }
   switch (kind) {
-    case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, ctx->grid_wave, ctx->stream); break;
+    case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, shared_grid(ctx, ctx->grid_wave, 1), ctx->stream); break;
     case Kernel::Block:
       e = ctr::launch_chain(ctx->imp, a, split ? ctx->slices : 0,
-                            split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid, ctx->stream);
+                            shared_grid(ctx, split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid, 1),
+                            ctx->stream);
       break;
-    case Kernel::Stream: e = ctr::launch_chain_big(ctx->imp, a, ctx->xbuf, ctx->grid_big, ctx->stream); break;
+    case Kernel::Stream:
+      e = ctr::launch_chain_big(ctx->imp, a, ctx->xbuf, shared_grid(ctx, ctx->grid_big, 1), ctx->stream);
+      break;
     case Kernel::Group: e = hipErrorInvalidValue; break;  // handled by enqueue_grouped
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "chain kernel");
@@ -441,6 +454,7 @@ bool context_loaded(const ctr_ctx* ctx) { return ctx && ctx->loaded; }
 double context_beta(const ctr_ctx* ctx) { return ctx->beta; }
 int context_nops(const ctr_ctx* ctx) { return ctx->nops; }
 size_t context_free_scratch(const ctr_ctx* ctx) { return ctx->arena_bytes - ctx->resident; }
+void context_set_grid_share(ctr_ctx* ctx, double share) { ctx->grid_share = share; }
 size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops) {
   return scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
          (size_t)n_ops * (sizeof(double) + sizeof(int32_t));

@@ -179,6 +179,8 @@ double context_beta(const ctr_ctx* ctx);
 int context_nops(const ctr_ctx* ctx);
 size_t context_free_scratch(const ctr_ctx* ctx);          // arena bytes not held by the impurity
 size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops);  // per-call scratch of one configuration
+// Fraction in (0, 1] of every persistent grid the context launches (1 = the whole device).
+void context_set_grid_share(ctr_ctx* ctx, double share);
 
 constexpr int kGroupCloseCols = 64;
 // Work items of a round are spread over this many counters (item i belongs to

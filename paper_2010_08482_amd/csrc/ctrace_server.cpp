@@ -4,7 +4,10 @@
 // requests queue per impurity; when a worker's device pass ends it admits the
 // requests that arrived meanwhile, in arrival order, up to the batch limit
 // and the scratch budget, and evaluates them as one batch.  Different
-// impurities' passes run concurrently on their own streams.
+// impurities' passes run concurrently on their own streams.  An optional grid
+// share per impurity launches only that fraction of each persistent grid, so
+// the workgroups of one impurity's long pass leave slots on the device where
+// another impurity's kernels start without waiting for that pass to end.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -134,6 +137,9 @@ ctr_status ctr_server_create(ctr_ctx* const* ctxs, int32_t n_ctx, const ctr_serv
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return CTR_ERR_ARG;  // one worker per context
   }
+  if (opts->grid_share)
+    for (int i = 0; i < n_ctx; ++i)
+      if (!(opts->grid_share[i] > 0.0 && opts->grid_share[i] <= 1.0)) return CTR_ERR_ARG;
   ctr_server* srv = new ctr_server();
   srv->max_batch = opts->max_batch;
   srv->max_pending = opts->max_pending;
@@ -145,6 +151,7 @@ ctr_status ctr_server_create(ctr_ctx* const* ctxs, int32_t n_ctx, const ctr_serv
     L->nops = ctr::context_nops(ctxs[i]);
     const size_t free_bytes = ctr::context_free_scratch(ctxs[i]);
     L->budget = opts->hbm_budget ? std::min(opts->hbm_budget, free_bytes) : free_bytes;
+    ctr::context_set_grid_share(ctxs[i], opts->grid_share ? opts->grid_share[i] : 1.0);
     srv->lanes.push_back(std::move(L));
   }
   for (auto& L : srv->lanes) L->worker = std::thread(run_lane, srv, L.get());
@@ -216,6 +223,7 @@ void ctr_server_destroy(ctr_server* srv) {
   }
   for (auto& L : srv->lanes)
     if (L->worker.joinable()) L->worker.join();
+  for (auto& L : srv->lanes) ctr::context_set_grid_share(L->ctx, 1.0);
   delete srv;
 }
 

@@ -50,7 +50,8 @@ class ctr_impurity(ctypes.Structure):
 
 
 class ctr_server_opts(ctypes.Structure):
-    _fields_ = [("max_batch", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t),
+                ("grid_share", ctypes.POINTER(ctypes.c_double))]
 
 
 class ctr_mc_opts(ctypes.Structure):
@@ -332,9 +333,15 @@ def ctr_tune(ctx, offsets, tau, op):
     return int(chosen.value), {k: float(ms[k]) for k in range(1, 5) if ms[k] >= 0}
 
 
-def ctr_server_create(ctxs, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0):
+def ctr_server_create(ctxs, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0,
+                      grid_share=None):
+    """grid_share: optional per-context fractions in (0, 1] of each persistent grid."""
     arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
-    o = ctr_server_opts(int(max_batch), int(max_pending), int(hbm_budget))
+    share = None if grid_share is None else np.ascontiguousarray(grid_share, dtype=np.float64)
+    if share is not None and share.size != len(ctxs):
+        raise ValueError("one grid share per context")
+    o = ctr_server_opts(int(max_batch), int(max_pending), int(hbm_budget),
+                        _ptr(share, ctypes.c_double) if share is not None else None)
     out = ctypes.c_void_p()
     st = _lib.ctr_server_create(arr, len(ctxs), ctypes.byref(o), ctypes.byref(out))
     if st != CTR_OK:
@@ -471,9 +478,11 @@ class MarkovChains:
 class TraceServer:
     """Continuous-batching server over TraceContexts (one worker per context)."""
 
-    def __init__(self, contexts, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0):
+    def __init__(self, contexts, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0,
+                 grid_share=None):
         self.contexts = list(contexts)
-        self.srv = ctr_server_create([c.ctx for c in self.contexts], max_batch, max_pending, hbm_budget)
+        self.srv = ctr_server_create([c.ctx for c in self.contexts], max_batch, max_pending, hbm_budget,
+                                     grid_share)
 
     def submit(self, impurity, tag, tau, op, log_threshold=-math.inf):
         return ctr_server_submit(self.srv, impurity, tag, tau, op, log_threshold)
@@ -506,9 +515,14 @@ def value_pair(v):
 
 
 class TraceContext:
-    """A ctrace context with its arena and stream taken from PyTorch."""
+    """A ctrace context with its arena and stream taken from PyTorch.
 
-    def __init__(self, table, arena_bytes: int | None = None, device: int = 0, scratch_bytes: int = 1 << 30):
+    stream: the torch.cuda.Stream the context enqueues on (default: the current
+    stream).  Contexts served together by a TraceServer overlap on the device
+    only when each has a stream of its own."""
+
+    def __init__(self, table, arena_bytes: int | None = None, device: int = 0, scratch_bytes: int = 1 << 30,
+                 stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -518,7 +532,7 @@ class TraceContext:
         if arena_bytes is None:
             arena_bytes = self.default_arena_bytes(table, scratch_bytes)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = ctr_create(self.device, self.arena.data_ptr(), self.arena.numel(), self.stream.cuda_stream)
         ctr_set_impurity(self.ctx, table)
 

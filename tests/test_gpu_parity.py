@@ -607,11 +607,16 @@ def test_fp32_split_rejects_unsupported_slices(lib, ctx):
 # serving: continuous batching over several impurities
 # ---------------------------------------------------------------------------
 
-def test_server_results_match_alone(lib, ctx):
+@pytest.mark.parametrize("own_streams,grid_share", [(False, None), (True, None), (True, (0.25, 0.75))])
+def test_server_results_match_alone(lib, ctx, own_streams, grid_share):
     """Requests for two impurities (real d-shell, complex p-shell), plain and
     lazy, submitted from four threads while earlier ones are on the GPU: every
-    result equals the same request evaluated alone, within the parity bar."""
+    result equals the same request evaluated alone, within the parity bar;
+    also with each impurity on a stream of its own (the passes overlap on the
+    device) and with each impurity's kernels launched on a share of their grids."""
     import threading
+
+    import torch
 
     tab_d, cd = ctx("dshell")
     tab_p, cp = ctx("pshell")
@@ -636,7 +641,11 @@ def test_server_results_match_alone(lib, ctx):
         reqs[i] = (k, s, thr)
         alone[i] = cd.lazy_batch(np.array([0, s.n]), s.tau, s.op, np.array([thr]))[0]
     order = rng.permutation(len(reqs))
-    srv = lib.TraceServer([cd, cp], max_batch=96)
+    served = [cd, cp]
+    if own_streams:
+        served = [lib.TraceContext(tab_d, stream=torch.cuda.Stream()),
+                  lib.TraceContext(tab_p, stream=torch.cuda.Stream())]
+    srv = lib.TraceServer(served, max_batch=96, grid_share=grid_share)
     try:
         def submit(part):
             for j in part:
@@ -654,6 +663,9 @@ def test_server_results_match_alone(lib, ctx):
         passes, evaluated = srv.stats()
     finally:
         srv.close()
+        if own_streams:
+            for c in served:
+                c.close()
     assert len(res) == len(reqs) and evaluated == len(reqs)
     assert np.all(res["status"] == 0)
     assert passes < len(reqs) and res["batch"].max() > 1   # requests were batched
