@@ -302,7 +302,7 @@ def cpu_block_sparse(tab, strings, seconds_budget=5.0):
             "sample": f"first {n_all} / {n_one} configurations, {el_all:.1f} s / {el_one:.1f} s"}
 
 
-def serve_main(args):
+def serve_main(args, emit: bool = True):
     """Serving mix: 256 Markov chains spread over the d-shell, f-shell (N, Jz)
     and, with --serve-cf, crystal-field f-shell impurities; trace requests arrive
     as a Poisson stream, each the chain's configuration after one pair
@@ -413,7 +413,9 @@ def serve_main(args):
     }
     for c in ctxs:
         c.close()
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def fp64_throughput(wl_id, n_configs, steps, warmup):
@@ -715,6 +717,15 @@ def main():
     if not args.no_also and args.workload == 1:
         name, rec = fp64_throughput(2, 0, 3, 1)
         line["also"] = {name: rec}
+        # the serving mix at one arrival rate, full grids (bench.py --serve for other settings)
+        sargs = argparse.Namespace(**{**vars(args), "serve_rate": 8000.0, "serve_seconds": 2.0,
+                                      "serve_grid_share": "", "serve_cf": False})
+        try:
+            sv = serve_main(sargs, emit=False)
+            line["serving"] = {k: sv[k] for k in ("value", "unit", "offered_rate", "completed", "statuses_ok",
+                                                  "device_passes", "latency_ms", "per_impurity", "config")}
+        except Exception as e:  # reported in the line; the trace measurement above stands
+            line["serving"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(line), flush=True)
 
 
