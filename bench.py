@@ -620,7 +620,9 @@ def main():
         per = flops / (split["chain_ms_per_step"] * 1e-3) / 1e12
         split["achieved_fp64_equivalent_tflops"] = per
         nprod = args.split_slices * (args.split_slices + 1) // 2
-        split["executed_fp32_tflops"] = nprod * per
+        # the slice products the method needs (nprod FP32 products per FP64 multiply-add); the matrix
+        # pipe also runs the padding of the 16-column tiles, which only hardware counters see
+        split["needed_fp32_tflops"] = nprod * per
         split["frac_fp32_peak"] = nprod * per / 157.3
     per_launch_ms = chain_ms / max(launches, 1)
     launches_per_step = launches / max(args.steps, 1)
