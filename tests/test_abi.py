@@ -56,3 +56,36 @@ def test_binding_names_match_header():
     src = open(os.path.join(ROOT, "paper_2010_08482_amd", "ctrace.py")).read()
     for name in declared_functions():
         assert f"def {name}(" in src, name
+
+
+STRUCTS = ("ctr_value", "ctr_opts", "ctr_impurity", "ctr_mc_opts", "ctr_server_opts", "ctr_result")
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets, as a C compiler lays them out (gcc on the header alone)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler on this host")
+    from paper_2010_08482_amd import ctrace
+
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ctrace.h"', "int main(void) {"]
+    for s in STRUCTS:
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for name, _ in getattr(ctrace, s)._fields_:
+            lines.append(f'  printf("{s} {name} %zu\\n", offsetof({s}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for s in STRUCTS:
+        st = getattr(ctrace, s)
+        assert got[(s, "size")] == ctypes.sizeof(st), s
+        for name, _ in st._fields_:
+            assert got[(s, name)] == getattr(st, name).offset, (s, name)
