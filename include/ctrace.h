@@ -84,7 +84,7 @@ typedef struct {
 enum {
   CTR_KERNEL_AUTO = 0,    /* the kernel ctr_tune picked, for non-lazy FP64 batches of at least a
                              quarter of its sample; otherwise FP64 with sectors <= 128 states: the
-                             wavefront kernel; else, for batches of >= 256 FP64 traces (lazy ones
+                             wavefront kernel; else, for batches of >= 48 FP64 traces (lazy ones
                              included), the block-grouped rounds when the sectors fit them and the
                              arena holds their scratch; else the LDS-resident workgroup kernel when
                              the panel fits LDS, else streaming */

@@ -132,8 +132,10 @@ bool carve(ctr_ctx* ctx, Bump& b, int n_cfg, BatchArgs& a) {
 enum class Kernel { Wave, Block, Stream, Group };
 
 // Smallest batch for which AUTO takes the block-grouped rounds: below it the
-// per-round launches cost more than the shared block reads save.
-constexpr int kGroupMinBatch = 256;
+// per-round launches cost more than the shared block reads save (f-shell,
+// 327-state sectors, host arrays: even at 32 configurations, grouped 21%
+// faster at 64 and 35% at 128).
+constexpr int kGroupMinBatch = 48;
 
 // Block-grouped rounds for the configurations of `a` (scratch after `b`'s
 // offset).  Returns CTR_ERR_OOM, with nothing enqueued past the plan, if the
