@@ -21,6 +21,7 @@ exp(log_scale).
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import scipy.linalg
@@ -118,11 +119,65 @@ def _chain(X, E, ops, tau, beta):
     return _close(X, logs)
 
 
-class DenseTrace:
-    """Full-space trace of one impurity in the eigenbasis of H_loc."""
+def _chain_live(D, dtype, E, get_op, tau, beta):
+    """trace() and abs_scale() of the same string in one pass, carrying only
+    the columns of the running products that are not yet zero.
 
-    def __init__(self, imp):
+    Every step acts on each column alone (propagator, operator, rescale), so a
+    column that an operator maps to zero stays zero and can be dropped; the
+    trace sums the diagonal entries of the columns that are left.  The live
+    set follows the modulus chain: |X| <= A entrywise for the running
+    products X and A of the two chains, so a zero column of A is a zero
+    column of X.  get_op(j) returns operator j of the string as a dense
+    matrix."""
+    idx = np.arange(D)
+    X = np.eye(D, dtype=dtype)
+    A = np.eye(D)
+    logs = np.zeros(D)
+    loga = np.zeros(D)
+    prev = 0.0
+    for j, t in enumerate(tau):
+        X, logs = _propagate(X, E, float(t) - prev, logs)
+        A, loga = _propagate(A, E, float(t) - prev, loga)
+        O = get_op(j)
+        X = O @ X
+        A = np.abs(O) @ A
+        del O
+        keep = np.any(A != 0, axis=0)
+        if not np.all(keep):
+            idx, X, A, logs, loga = idx[keep], X[:, keep], A[:, keep], logs[keep], loga[keep]
+        X, logs = _rescale(X, logs)
+        A, loga = _rescale(A, loga)
+        prev = float(t)
+        if idx.size == 0:
+            return (0.0, 0.0), (0.0, 0.0)
+    X, logs = _propagate(X, E, beta - prev, logs)
+    A, loga = _propagate(A, E, beta - prev, loga)
+
+    def close(M, lg):
+        d = M[idx, np.arange(idx.size)]
+        live = d != 0
+        if not np.any(live):
+            return 0.0, 0.0
+        lmax = float(np.max(lg[live]))
+        tr = np.sum(d[live] * np.exp(lg[live] - lmax))
+        return (complex(tr) if np.iscomplexobj(tr) else float(tr)), lmax
+
+    return close(X, logs), close(A, loga)
+
+
+class DenseTrace:
+    """Full-space trace of one impurity in the eigenbasis of H_loc.
+
+    op_store: optional directory.  The annihilator matrices in the eigenbasis
+    are then written there as .npy files once and memory-mapped back on use
+    instead of being kept in memory (a 2^14-state complex operator takes
+    4 GiB); a creator is the conjugate transpose of its annihilator (the
+    Jordan-Wigner matrices are real, so c+ = c^T)."""
+
+    def __init__(self, imp, op_store: str | None = None):
         self.imp = imp
+        self.op_store = op_store
         self.nf = imp.n_flavors
         self.beta = float(imp.beta)
         H = hamiltonian_sparse(imp.h1, imp.U)
@@ -135,6 +190,14 @@ class DenseTrace:
 
     def op_matrix(self, code: int) -> np.ndarray:
         """Operator 'code' in the eigenbasis: <a| O |b> = (V^H O V)_ab."""
+        if self.op_store is not None:
+            path = os.path.join(self.op_store, f"c{code // 2}.npy")
+            if not os.path.exists(path):
+                C = operator(self.nf, code - code % 2)
+                np.save(path + ".tmp.npy", self.V.conj().T @ (C @ self.V))
+                os.replace(path + ".tmp.npy", path)
+            M = np.load(path, mmap_mode="r")
+            return np.array(M) if code % 2 == 0 else M.conj().T
         if code not in self._ops:
             C = operator(self.nf, code)
             self._ops[code] = self.V.conj().T @ (C @ self.V)
@@ -155,6 +218,15 @@ class DenseTrace:
         tau, op = _check_string(tau, op, self.beta, self.nf)
         D = self.E.shape[0]
         return _chain(np.eye(D), self.E, [np.abs(self.op_matrix(int(o))) for o in op], tau, self.beta)
+
+    def trace_and_scale(self, tau, op):
+        """(trace(tau, op), abs_scale(tau, op)) from one pass over the string
+        that drops the columns of the running products once they are zero
+        (same per-column arithmetic; see _chain_live).  Used for the
+        full-size impurities, where a column of the product costs 2^14 rows."""
+        tau, op = _check_string(tau, op, self.beta, self.nf)
+        D = self.E.shape[0]
+        return _chain_live(D, self.dtype, self.E, lambda j: self.op_matrix(int(op[j])), tau, self.beta)
 
     def partition_function(self):
         """Order zero: Z = Tr exp(-beta H) as (mantissa, log_scale)."""

@@ -81,6 +81,29 @@ def low_order_set(name, impurity, seed, orders):
     return {"impurity": impurity, "seed": seed, "records": out}
 
 
+def workload_set(name, impurity, config_id, indices, store):
+    """Workload strings of a full-size impurity at production order, through
+    the oracle's memory-bounded route (operator matrices on disk under
+    `store`, zero columns dropped).  The file is rewritten after every string."""
+    imp = make_impurity(impurity)
+    t0 = time.time()
+    os.makedirs(store, exist_ok=True)
+    dt = DenseTrace(imp, op_store=store)
+    print(f"{name}: eigenbasis in {time.time() - t0:.0f}s", flush=True)
+    cfgs = make_configs(config_id, max(indices) + 1)
+    out = []
+    for i in indices:
+        s = cfgs[i]
+        (m, l), (a, la) = dt.trace_and_scale(s.tau, s.op)
+        m = complex(m)
+        out.append({"i": int(i), "n": int(s.n), "re": m.real, "im": m.imag, "log_scale": l, "abs": a,
+                    "abs_log": la, "tau": s.tau.tolist(), "op": s.op.tolist()})
+        with open(os.path.join(HERE, name + ".json"), "w") as fh:
+            json.dump({"impurity": impurity, "config_id": config_id, "records": out}, fh, indent=0)
+        print(f"{name}: configuration {i} (order {s.n}) {time.time() - t0:.0f}s", flush=True)
+    return {"impurity": impurity, "config_id": config_id, "records": out}
+
+
 SETS = {
     # d-shell workload strings (the benchmark's configurations), first 256
     "dshell_config1": lambda: config_set("dshell_config1", "dshell", 1, 256),
@@ -91,6 +114,10 @@ SETS = {
     # the generic f-shell impurities of the (N, Jz) and crystal-field workloads at full size
     "fshell_low": lambda: low_order_set("fshell_low", "fshell", 81, [2, 2, 2, 4]),
     "fshell_cf_low": lambda: low_order_set("fshell_cf_low", "fshell_cf", 82, [2, 2, 4]),
+    # production-order workload strings of the f-shell (N, Jz) benchmark (orders 44 and 40; the two
+    # cheapest for the dense oracle among its first 400 configurations of order <= 44)
+    "fshell_workload": lambda: workload_set("fshell_workload", "fshell", 2, [93, 391],
+                                            os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell")),
 }
 
 if __name__ == "__main__":

@@ -192,3 +192,266 @@ def test_label_walk_zero_strings_have_zero_trace(k2):
         surv = label_walk(imp, c.op, table)
         if not surv:
             assert dt.trace(c.tau, c.op)[0] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# cancellation scales, the component-wise eigensolve at beta = 50, both
+# directions of the label walk, and the memory-bounded route
+# ---------------------------------------------------------------------------
+
+def _dd_pshell():
+    from workloads.impurity import _density_density
+    return _density_density("dd_pshell", 3, 8.0, 311, "NS", False)
+
+
+@pytest.mark.parametrize("which", ["dd_dshell", "dd_pshell"])
+def test_abs_scale_is_the_modulus_sum_of_the_enumeration(which):
+    """For an occupation-diagonal H every Lehmann term of w_loc is one signed
+    path of the bit enumeration, so A = sum of |terms| is the enumeration with
+    the signs dropped.  (All paths of one string share their sign there, so
+    A = |w|: negative traces catch a dropped modulus.)  Log scales reach
+    ~2.5e3 at beta = 50, where every exp(l - M) carries ~2.5e3 ulp of
+    rounding: bar 5e-12."""
+    imp = make_impurity(which) if which == "dd_dshell" else _dd_pshell()
+    dt = DenseTrace(imp)
+    rng = np.random.Generator(np.random.PCG64(23))
+    checked = negative = 0
+    for _ in range(14):
+        s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 12)), "alternating")
+        a = dt.abs_scale(s.tau, s.op)
+        m = densdens_trace(imp, s.tau, s.op, moduli=True)
+        t = densdens_trace(imp, s.tau, s.op)
+        if m[0] == 0:
+            assert a[0] == 0
+            continue
+        checked += 1
+        assert a[0] > 0
+        assert rel_err(a, m) < 5e-12
+        negative += t[0] < 0
+    assert checked >= 8 and negative >= 2
+
+
+def _lehmann_modulus_sum(dt, tau, op):
+    """sum over all eigenstate paths a_0 -> a_1 -> ... -> a_n = a_0 of
+    prod_j |<a_j+1| O_j |a_j>| exp(-dtau_j (E_a_j - E0)), enumerated path by
+    path (16^n paths), as (value, log_scale) with log_scale = -beta E0."""
+    n = len(op)
+    D = dt.E.shape[0]
+    E = dt.E - dt.E0
+    gaps = np.diff(np.concatenate([[0.0], tau]))
+    gaps[0] += dt.beta - tau[-1]               # P(tau_1) and P(beta - tau_n) both act on a_0
+    paths = np.indices((D,) * n).reshape(n, -1)  # paths[j] = a_j
+    w = np.ones(paths.shape[1])
+    for j in range(n):
+        M = np.abs(dt.op_matrix(int(op[j])))
+        w *= M[paths[(j + 1) % n], paths[j]] * np.exp(-gaps[j] * E[paths[j]])
+    return float(np.sum(w)), -dt.beta * dt.E0
+
+
+def test_abs_scale_is_the_lehmann_modulus_sum_with_cancellation(k2):
+    """Kanamori atom (spin flips and pair hopping: eigenstates are
+    superpositions, so terms of one string carry different signs): A from the
+    modulus chain against the path-by-path sum of |terms| at orders 2 and 4."""
+    imp, dt = k2
+    rng = np.random.Generator(np.random.PCG64(31))
+    checked = cancelling = 0
+    for i in range(24):
+        s = random_string(rng, 4, imp.beta, 2 if i % 3 == 0 else 4, "random")
+        a = dt.abs_scale(s.tau, s.op)
+        w = dt.trace(s.tau, s.op)
+        ref = _lehmann_modulus_sum(dt, s.tau, s.op)
+        if ref[0] == 0:
+            assert a[0] == 0
+            continue
+        checked += 1
+        assert rel_err(a, ref) < 1e-12
+        cancelling += abs(complex(w[0])) * math.exp(w[1] - a[1]) < 0.9 * a[0]
+    assert checked >= 12 and cancelling >= 3
+
+
+def _brute_histogram_moduli(imp, tau, op, n_labels):
+    """The path enumeration of the density-density histogram with every path
+    weight replaced by its modulus (the interval sums of moduli)."""
+    nf = imp.n_flavors
+    eps = np.real(np.diag(np.asarray(imp.h1)))
+    V = np.asarray(imp.params["V"])
+    num = np.zeros(n_labels)
+    den = 0.0
+    for s0 in range(1 << nf):
+        s, sign, t_prev = s0, 1.0, 0.0
+        segs = []
+        alive = True
+        for t, o in zip(tau, op):
+            segs.append((t - t_prev, s))
+            f, dag = int(o) // 2, int(o) % 2
+            if ((s >> f) & 1) == dag:
+                alive = False
+                break
+            if bin(s & ((1 << f) - 1)).count("1") % 2:
+                sign = -sign
+            s ^= 1 << f
+            t_prev = t
+        if not alive or s != s0:
+            continue
+        segs.append((imp.beta - t_prev, s))
+        expo = 0.0
+        for dtau, st in segs:
+            n = np.array([(st >> f) & 1 for f in range(nf)], dtype=float)
+            expo += dtau * (eps @ n + 0.5 * n @ V @ n)
+        wgt = math.exp(-expo)
+        den += sign * wgt
+        for dtau, st in segs:
+            num[bin(st).count("1")] += wgt * dtau
+    return num / (imp.beta * abs(den))
+
+
+def test_label_histogram_abs_is_the_modulus_enumeration():
+    from oracle.fock import occupations
+    from oracle.observables import label_histogram_abs, label_projectors
+
+    imp = _dd_pshell()
+    dt = DenseTrace(imp)
+    lab = occupations(imp.n_flavors).sum(axis=1).astype(np.int64)
+    P = label_projectors(dt, lab, imp.n_flavors + 1)
+    rng = np.random.Generator(np.random.PCG64(304))
+    checked = 0
+    for _ in range(10):
+        s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 4)), "alternating")
+        if dt.trace(s.tau, s.op)[0] == 0:
+            continue
+        got = label_histogram_abs(dt, s.tau, s.op, P)
+        ref = _brute_histogram_moduli(imp, s.tau, s.op, imp.n_flavors + 1)
+        assert np.all(got >= 0)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * max(1.0, float(np.max(ref)))
+        checked += 1
+    assert checked >= 4
+
+
+def test_expm_route_matches_eigen_route_dshell_beta50():
+    """The component-wise eigensolve (each connected component of H's nonzero
+    pattern diagonalised alone, which the d-shell at beta = 50 needs) against
+    scipy's matrix exponential in the occupation basis, which uses no
+    eigendecomposition: the 20 lowest-order workload strings of the d-shell
+    benchmark (orders 20-22, 1024 states)."""
+    imp = make_impurity("dshell")
+    dt = DenseTrace(imp)
+    cfgs = make_configs(1, 400)
+    low = sorted(range(len(cfgs)), key=lambda i: (cfgs[i].n, i))[:20]
+    nonzero = 0
+    for i in low:
+        c = cfgs[i]
+        a, b = dt.trace(c.tau, c.op), expm_trace(imp, c.tau, c.op)
+        if a[0] == 0 and b[0] == 0:
+            continue
+        nonzero += 1
+        assert rel_err(a, b) < 1e-10, (i, c.n)
+    assert nonzero >= 15
+
+
+def _reachable_start_labels(imp, op):
+    """Start labels whose walk survives, by brute force over occupation states
+    (bits, not the label table): from the states of label k, the labels of the
+    states an operator leaves nonzero; the walk dies when that set is empty and
+    survives if label k is among the labels reached at the end."""
+    nf = imp.n_flavors
+    qn = np.asarray(imp.qn)
+    lab = [tuple(int(v) for v in ((np.array([(s >> (nf - 1 - f)) & 1 for f in range(nf)]) @ qn.T)))
+           for s in range(1 << nf)]
+    groups = {}
+    for s, k in enumerate(lab):
+        groups.setdefault(k, []).append(s)
+    out = []
+    for k0 in sorted(groups):
+        cur = {k0}
+        for o in op:
+            f, dag = int(o) // 2, int(o) % 2
+            bit = 1 << (nf - 1 - f)      # flavor 0 is the most significant bit (Jordan-Wigner order)
+            nxt = set()
+            for k in cur:
+                for s in groups[k]:
+                    if bool(s & bit) != bool(dag):
+                        nxt.add(lab[s ^ bit])
+            cur = nxt
+            if not cur:
+                break
+        if k0 in cur:
+            out.append(k0)
+    return out
+
+
+@pytest.mark.parametrize("name,rule", [("kanamori2", "random"), ("pshell", "alternating"), ("pshell_cf", "random")])
+def test_label_walk_equals_state_reachability(name, rule):
+    """Both directions of the label walk against brute force over occupation
+    states (no label table): a label survives exactly when some chain of
+    states with nonzero operator action leads from it back to it."""
+    imp = make_impurity(name)
+    table = label_table(imp)
+    rng = np.random.Generator(np.random.PCG64(37))
+    kept = 0
+    for _ in range(40):
+        s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 6)), rule)
+        got = label_walk(imp, s.op, table)
+        assert got == _reachable_start_labels(imp, s.op)
+        kept += len(got)
+    assert kept >= 20
+
+
+@pytest.mark.parametrize("rule", ["random", "alternating"])
+def test_label_walk_survivors_carry_weight(rule):
+    """Survivor direction on the trace itself: in the crystal-field p-shell,
+    every label group (N) is one connected component of H_loc, so propagators
+    at generic times mix all states of a label and no surviving label can
+    cancel.  With the projector P_k inserted at time 0 (it commutes with
+    H_loc) the trace sums the start states of label k: exactly zero for every
+    label the walk kills, nonzero for every label it keeps."""
+    from scipy.sparse.csgraph import connected_components
+
+    from oracle.hamiltonian import hamiltonian_sparse
+    from oracle.labels import state_labels
+    from oracle.observables import _inserted, label_projectors
+
+    imp = make_impurity("pshell_cf")
+    n_comp, _ = connected_components((abs(hamiltonian_sparse(imp.h1, imp.U)) > 0).astype(np.int8), directed=False)
+    table = label_table(imp)
+    keys = table[0]
+    assert n_comp == len(keys)
+    dt = DenseTrace(imp)
+    ids = np.array([keys.index(tuple(int(v) for v in row)) for row in state_labels(imp)])
+    P = label_projectors(dt, ids, len(keys))
+    rng = np.random.Generator(np.random.PCG64(29))
+    kept = killed = 0
+    for _ in range(12):
+        s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 5)), rule)
+        surv = set(label_walk(imp, s.op, table))
+        for k, key in enumerate(keys):
+            m, _ = _inserted(dt, s.tau, s.op, 0, 0.0, P[k])
+            if key in surv:
+                assert m != 0, (s.op, key)
+                kept += 1
+            else:
+                assert m == 0, (s.op, key)
+                killed += 1
+    assert kept >= 10 and killed >= 10
+
+
+@pytest.mark.parametrize("name", ["pshell", "pshell_cf", "kanamori2"])
+def test_memory_bounded_route_matches_the_plain_route(name, tmp_path):
+    """trace_and_scale (operators on disk, creators as adjoints, zero columns
+    dropped) against trace() and abs_scale(); random types make many columns
+    die along the way."""
+    imp = make_impurity(name)
+    d0 = DenseTrace(imp)
+    d1 = DenseTrace(imp, op_store=str(tmp_path))
+    rng = np.random.Generator(np.random.PCG64(5))
+    nz = 0
+    for i in range(24):
+        s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 8)),
+                          "random" if i % 2 else "alternating")
+        a, b = d0.trace(s.tau, s.op), d0.abs_scale(s.tau, s.op)
+        x, y = d1.trace_and_scale(s.tau, s.op)
+        if a[0] == 0:
+            assert x[0] == 0
+            continue
+        nz += 1
+        assert rel_err(x, a) < 1e-12 and rel_err(y, b) < 1e-12
+    assert nz >= 12
