@@ -1,12 +1,16 @@
 """Throughput benchmark of the CT-HYB local trace on one MI355X.
 
 One step = one pass of the whole trace path (sector-string walk, rotation,
-lazy bounds, block-product chains, close, merge) over the batch of 10^4
-d-shell configurations (5-orbital Kanamori impurity with spin-flip and pair
-hopping, 1024 states, (N, Sz) sectors with largest block 100, beta = 50,
-orders 20..80), inputs already resident in HBM.  Prints one JSON line.
+lazy bounds, block-product chains, close, merge) over one batch of
+configurations, inputs already resident in HBM.  The default workload is the
+crystal-field f-shell: 14 flavors, 16384 states, Slater-Condon interaction,
+spin-orbit coupling and a random Hermitian crystal field (sectors by N only,
+largest block 3432), beta = 40, 2000 configurations at orders 60..200, complex
+FP64; 200 configurations per step, so the 10 timed steps cover all 2000.
+The d-shell (5-orbital Kanamori, 1024 states) and the f-shell (N, Jz)
+workloads run as side legs in the same line.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--cpu-sample S] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--batch B] [--workload 1|2|3] [--no-cpu]
 """
 
 from __future__ import annotations
@@ -81,20 +85,17 @@ def algorithmic_flops(tab, strings):
     return total
 
 
-def chain_kernel_name(tab, n_cfg):
-    """Kernel the library's automatic choice runs for a batch of FP64 traces of
-    this table: the wavefront kernel for sectors of at most 128 states, else
-    block-grouped rounds for batches of at least 256 traces with sectors of at
-    most 384 states, else the LDS workgroup kernel while a 16-column panel fits
-    LDS, the streaming kernel beyond."""
+def kernel_name(tab, kernel, slices):
+    """Name of the chain kernel behind a CTR_KERNEL_* code the library reports
+    for its last call (ctr_last_kernel): the grouped rounds keep every row of a
+    block in one wavefront up to 32 (complex) / 128 (real) rows and in one
+    workgroup up to 384, the row-chunked items cover any size."""
     xr = (tab.max_dim + 15) // 16 * 16
-    if xr <= 128:
-        return "k_chain_wave"
-    if n_cfg >= 256 and xr <= 384:
-        return "k_gstep"
-    if xr <= (576 if tab.is_complex else 1024):
-        return "k_chain"
-    return "k_chain_big"
+    if kernel == 4:
+        return "k_gstep_wave" if xr <= (32 if tab.is_complex else 128) else "k_gstep"
+    names = {1: "k_chain_wave", 2: "k_chain", 3: "k_chain_big", 5: "k_gbig"}
+    name = names.get(kernel, f"kernel {kernel}")
+    return name + ("_split" if slices and kernel == 5 else "")
 
 
 # HBM-side bytes per launch of the dominant kernel (FETCH_SIZE + WRITE_SIZE from
@@ -102,14 +103,10 @@ def chain_kernel_name(tab, n_cfg):
 # per workload, valid only for the kernel source they were measured on: any
 # change to that source makes the figure stale (reported as None).
 TRAFFIC_MEASURED = {
-    ("k_chain_wave", "dshell-kanamori-10^4-orders20-80"): {
+    ("k_chain_wave", "dshell-kanamori-10^4-orders20-80, 10000 per step"): {
         "source": "ctrace_kernels.hip",
         "sha256": "213e78688ec5b1bcafdd25921e57229a61c5a9489d9987da0d95e4da625eeaf7",
         "bytes": 73.0208e9},
-    ("k_gstep", "fshell-slater-soc-10^4-orders40-160 (first 2000)"): {
-        "source": "ctrace_group.hip",
-        "sha256": "113c6a6c7845771d8b1a9036f00ac0128750884f8b42f6e9bfe33b5ef72f36b4",
-        "bytes": 6.9142e9},
 }
 
 
@@ -418,10 +415,33 @@ def serve_main(args, emit: bool = True):
     return line
 
 
-def fp64_throughput(wl_id, n_configs, steps, warmup):
-    """FP64 throughput of another workload in the same run (device batch,
-    inputs resident, AUTO kernel): traces/s, chain time per launch and the
-    roofline figures, for the line's "also" object."""
+def _rel_errors(a, b):
+    """Relative differences |a - b| / |b| and against the cancellation scale
+    exp(log_abs) of b, over the configurations where b is nonzero."""
+    rel, rel_a = [], []
+    for x, y in zip(a, b):
+        if y["re"] == 0 and y["im"] == 0:
+            continue
+        M = max(x["log_scale"], y["log_scale"])
+        u = complex(x["re"], x["im"]) * math.exp(x["log_scale"] - M)
+        v = complex(y["re"], y["im"]) * math.exp(y["log_scale"] - M)
+        rel.append(abs(u - v) / abs(v))
+        rel_a.append(abs(u - v) / math.exp(y["log_abs"] - M))
+    return np.array(rel), np.array(rel_a)
+
+
+def _dist(x):
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "max": float(x.max()),
+            "n": int(x.size)} if x.size else None
+
+
+def throughput_leg(wl_id, n_configs, batch, steps, warmup, kernel_opt, split_configs, split_slices, lazy_sample,
+                   no_cpu, headline):
+    """FP64 throughput of one workload through the device entry point (inputs
+    resident in HBM): `steps` timed steps, step k evaluating batch k (cycling)
+    of `batch` configurations; chain-kernel time from HIP events on the
+    library's stream; the roofline of the dominant kernel; an FP32-split leg on
+    the first `split_configs` configurations; a lazy leg; the CPU oracle."""
     import torch
 
     from paper_2010_08482_amd import ctrace
@@ -430,75 +450,187 @@ def fp64_throughput(wl_id, n_configs, steps, warmup):
     from workloads.configs import pack
 
     wl = WORKLOADS[wl_id]
-    tab = build_sectors(make_impurity(wl["impurity"]))
+    imp = make_impurity(wl["impurity"])
+    tab = build_sectors(imp)
     strings = make_configs(wl["config_id"], n_configs or None)
     n_cfg = len(strings)
+    B = min(batch or n_cfg, n_cfg)
+    n_batches = (n_cfg + B - 1) // B
     name = wl["name"] if not n_configs else f"{wl['name']} (first {n_cfg})"
-    print(f"[bench] also: {name}", file=sys.stderr, flush=True)
+    covered = min(steps, n_batches) * B
+    print(f"[bench] {name}: {n_cfg} configurations, {tab.n_sectors} sectors, largest block {tab.max_dim}, "
+          f"{B} per step", file=sys.stderr, flush=True)
     free, _ = torch.cuda.mem_get_info(0)
-    ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
+    # per-call scratch: the grouped rounds keep every surviving string's carried matrix resident
+    ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free * 0.55, 150 << 30)))
+    peaks = ctrace.ctr_probe_peaks(ctx.ctx) if headline else None
     offs, tau, op = pack(strings)
     dev = "cuda:0"
     d_offs, d_tau, d_op = (torch.from_numpy(a).to(dev) for a in (offs, tau, op))
-    d_out = torch.zeros(n_cfg * ctrace.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    vsz = ctrace.VALUE_DTYPE.itemsize
+    d_out = torch.zeros(n_cfg * vsz, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
 
-    def step():
-        ctrace.ctr_trace_batch_device(ctx.ctx, n_cfg, d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
-                                      d_out.data_ptr())
+    def run(b, precision=ctrace.CTR_FP64, out=None, count=None, slices=0):
+        c0 = (b % n_batches) * B
+        m = min(B, n_cfg - c0) if count is None else count
+        ctrace.ctr_trace_batch_device(ctx.ctx, m, d_offs.data_ptr() + 8 * c0, d_tau.data_ptr(), d_op.data_ptr(),
+                                      (out if out is not None else d_out).data_ptr() + vsz * c0, precision,
+                                      kernel_opt if precision == ctrace.CTR_FP64 else ctrace.CTR_KERNEL_AUTO, slices)
+        return m
 
-    for _ in range(warmup):
-        step()
+    for k in range(warmup):
+        run(k)
     torch.cuda.synchronize()
     ctrace.ctr_kernel_timing(ctx.ctx, True)
     ctrace.ctr_kernel_timing_read(ctx.ctx)
+    torch.cuda.synchronize()
+    done = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
+    for k in range(steps):
+        done += run(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     chain_ms, launches = ctrace.ctr_kernel_timing_read(ctx.ctx)
     ctrace.ctr_kernel_timing(ctx.ctx, False)
-    ctx.close()
-    flops = algorithmic_flops(tab, strings)
+    kcode, _ = ctrace.ctr_last_kernel(ctx.ctx)
+    kname = kernel_name(tab, kcode, 0)
+    flops = sum(algorithmic_flops(tab, strings[(k % n_batches) * B:(k % n_batches) * B + B]) for k in range(steps))
+    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)
+    print(f"[bench] {steps} steps in {elapsed:.3f}s; {kname} {chain_ms / max(launches, 1):.3f} ms per launch over "
+          f"{launches} launches", file=sys.stderr, flush=True)
     per_launch = chain_ms / max(launches, 1)
-    lps = launches / max(steps, 1)
-    achieved = flops / lps / (per_launch * 1e-3) / 1e12 if per_launch > 0 else None
-    kname = chain_kernel_name(tab, n_cfg)
-    cpu = cpu_oracle_extrapolated(tab, strings)
-    return name, {"value": n_cfg * steps / elapsed, "unit": "trace evals/s", "steps": steps, "warmup": warmup,
-                  "cpu_baseline_extrapolated": cpu,
-                  "ms_per_step": elapsed / steps * 1e3, "dtype": "c128" if tab.is_complex else "f64",
-                  "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                               "frac": achieved / PEAK_FP64_TFLOPS if achieved else None,
-                               "traffic": measured_traffic(kname, name), "kernel": kname,
-                               "algorithmic_flop_per_launch": flops / lps, "launch_ms": per_launch}}
+    achieved = flops / (chain_ms * 1e-3) / 1e12 if chain_ms > 0 else None
+    workload_key = f"{name}, {B} per step"
+    rec = {
+        "value": done / elapsed, "unit": "trace evals/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "dtype": "c128" if tab.is_complex else "f64",
+        "config": {"workload": workload_key + (f", {steps} steps cover {covered} of {n_cfg}" if steps else ""),
+                   "impurity": wl["impurity"], "n_configs": n_cfg, "configs_per_step": B,
+                   "sectors": int(tab.n_sectors), "largest_block": int(tab.max_dim), "beta": tab.beta,
+                   "complex": bool(tab.is_complex), "precision": "FP64"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS if achieved else None,
+                     "traffic": measured_traffic(kname, workload_key), "kernel": kname,
+                     "algorithmic_flop_per_launch": flops / max(launches, 1), "launch_ms": per_launch,
+                     "launches": launches, "chain_ms": chain_ms},
+        "measured_peaks": peaks,
+    }
+
+    if split_configs:
+        # FP32-split leg: block products on FP32 MFMA over exact 8-bit slices, first configurations
+        m = min(split_configs, n_cfg)
+        d_s = torch.zeros_like(d_out)
+        d_f = torch.zeros_like(d_out)
+        run(0, ctrace.CTR_FP64, d_f, m)
+        run(0, ctrace.CTR_FP32_SPLIT, d_s, m, split_slices)
+        torch.cuda.synchronize()
+        ctrace.ctr_kernel_timing(ctx.ctx, True)
+        ctrace.ctr_kernel_timing_read(ctx.ctx)
+        ts = time.perf_counter()
+        run(0, ctrace.CTR_FP32_SPLIT, d_s, m, split_slices)
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - ts
+        ms_s, n_s = ctrace.ctr_kernel_timing_read(ctx.ctx)
+        ctrace.ctr_kernel_timing(ctx.ctx, False)
+        ks, sl = ctrace.ctr_last_kernel(ctx.ctx)
+        outs = np.frombuffer(d_s.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)[:m]
+        outf = np.frombuffer(d_f.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)[:m]
+        rel_s, rel_a = _rel_errors(outs, outf)
+        fl = algorithmic_flops(tab, strings[:m])
+        per = fl / (ms_s * 1e-3) / 1e12 if ms_s > 0 else 0.0
+        nprod = sl * (sl + 1) // 2
+        rec["fp32_split"] = {
+            "value": m / el_s, "unit": "trace evals/s", "configurations": m, "slice_bits": 8, "slices": sl,
+            "kernel": kernel_name(tab, ks, sl), "fp32_products_per_fma": nprod, "chain_ms": ms_s,
+            "achieved_fp64_equivalent_tflops": per,
+            # the slice products the method needs (nprod FP32 products per FP64 multiply-add)
+            "needed_fp32_tflops": nprod * per, "frac_fp32_peak": nprod * per / 157.3,
+            "rel_err_vs_fp64": _dist(rel_s), "err_vs_fp64_over_abs_sum": _dist(rel_a),
+            "meets_1e-10": bool(np.all((rel_s <= 1e-10) | (rel_a <= 1e-12))) if rel_s.size else None}
+
+    if lazy_sample:
+        lz = strings[:lazy_sample]
+        full = ctx.trace_batch(lz)
+        rec["lazy"] = lazy_leg(ctx, imp, lz, full)
+
+    if not no_cpu:
+        if wl_id == 1:
+            sample = strings[:24]
+            rate, got, el, threads, refs = cpu_baseline(imp, sample)
+            rec["cpu_baseline"] = {"value": rate, "unit": "trace evals/s", "cores": threads, "kind": "oracle",
+                                   "sample": f"first {got} of the {n_cfg} configurations, dense 2^10-dim FP64 "
+                                             f"chain, {el:.1f} s"}
+            errs = []
+            for v, ref in zip(out[:got], refs):
+                if ref[0] == 0:
+                    continue
+                M = max(v["log_scale"], ref[1])
+                a = complex(v["re"], v["im"]) * math.exp(v["log_scale"] - M)
+                b = complex(ref[0]) * math.exp(ref[1] - M)
+                errs.append(abs(a - b) / abs(b))
+            rec["rel_err_vs_oracle_sample"] = _dist(np.array(errs))
+            rec["cpu_block_sparse"] = cpu_block_sparse(tab, strings)
+        else:
+            # a 2^14-state dense trace takes hours on the host: the oracle's cost per
+            # operator is timed on a smaller product and scaled (labelled extrapolated)
+            rec["cpu_baseline"] = cpu_oracle_extrapolated(tab, strings)
+    ctx.close()
+    return name, rec
+
+
+def dshell_extras(args):
+    """The d-shell workload's other legs: valence histogram, Markov chains
+    (lazy and full trace batches), single-configuration latency."""
+    from paper_2010_08482_amd import ctrace
+    from paper_2010_08482_amd.sectors import build_sectors
+    from workloads import make_configs, make_impurity
+
+    imp = make_impurity("dshell")
+    tab = build_sectors(imp)
+    strings = make_configs(1)
+    ctx = ctrace.TraceContext(tab, scratch_bytes=8 << 30)
+    rec = {"histogram": histogram_leg(ctx, tab, imp, strings)}
+    if args.mc_chains > 0:
+        mk = markov_leg(ctx, "dshell", strings, args.mc_chains, args.mc_steps)
+        mk["full_traces"] = markov_leg(ctx, "dshell", strings, args.mc_chains, args.mc_steps, True)
+        rec["markov"] = mk
+    lat = []
+    for s in strings[: args.latency_sample]:
+        t = time.perf_counter()
+        ctx.trace(s.tau, s.op)
+        lat.append((time.perf_counter() - t) * 1e3)
+    if lat:
+        rec["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "entry": "ctr_trace (one configuration, host pointers)"}
+    ctx.close()
+    return rec
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=-1,
+                    help="configurations per step (-1: 200 for the crystal-field f-shell, all otherwise)")
     ap.add_argument("--n-configs", type=int, default=0, help="use only the first N configurations (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-sample", type=int, default=200)
-    ap.add_argument("--no-split", action="store_true", help="skip the FP32-split leg")
+    ap.add_argument("--split-configs", type=int, default=-1,
+                    help="configurations of the FP32-split leg (-1: 16 crystal-field, 2000 f-shell, all d-shell; 0 = skip)")
     ap.add_argument("--split-slices", type=int, default=7, choices=[6, 7],
-                    help="8-bit slices per operand of the FP32-split leg (7 meets 1e-10 on every workload)")
-    ap.add_argument("--mc-chains", type=int, default=4096, help="chains of the Markov leg (0 = skip)")
-    ap.add_argument("--mc-steps", type=int, default=20, help="timed steps of the Markov leg")
-    ap.add_argument("--hist-sample", type=int, default=-1,
-                    help="configurations of the histogram leg (-1 = all, 0 = skip)")
+                    help="8-bit slices per operand of the FP32-split leg")
     ap.add_argument("--lazy-sample", type=int, default=-1,
-                    help="pair-insertion proposals for the lazy leg (-1 = every configuration, 0 = skip)")
+                    help="pair-insertion proposals of the lazy leg (-1: 100 crystal-field, all otherwise; 0 = skip)")
+    ap.add_argument("--mc-chains", type=int, default=4096, help="chains of the d-shell Markov leg (0 = skip)")
+    ap.add_argument("--mc-steps", type=int, default=20, help="timed steps of the Markov leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB once with a plain device copy (HBM counter calibration)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "wave", "block", "stream", "grouped"],
-                    help="chain kernel of the timed FP64 step (default: the library's automatic choice)")
-    ap.add_argument("--no-also", action="store_true",
-                    help="skip the second workload (the f-shell (N, Jz) step, reported under \"also\")")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "wave", "block", "stream", "grouped", "grouped_rows"],
+                    help="chain kernel of the timed FP64 steps (default: the library's automatic choice)")
+    ap.add_argument("--no-also", action="store_true", help="skip the side legs (d-shell, f-shell (N, Jz), serving)")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the throughput step")
     ap.add_argument("--serve-cf", action="store_true", help="serving mix: add the crystal-field f-shell")
     ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
@@ -519,207 +651,67 @@ def main():
     import torch
 
     from paper_2010_08482_amd import ctrace
-    from paper_2010_08482_amd.sectors import build_sectors
-    from workloads import make_configs, make_impurity
-    from workloads.configs import pack
-
-    wl = WORKLOADS[args.workload]
-    imp = make_impurity(wl["impurity"])
-    tab = build_sectors(imp)
-    strings = make_configs(wl["config_id"], args.n_configs or None)
-    n_cfg = len(strings)
-    print(f"[bench] workload {wl['name']}: {n_cfg} configurations, {tab.n_sectors} sectors, "
-          f"largest block {tab.max_dim}", file=sys.stderr, flush=True)
-
-    # per-call scratch: the grouped rounds keep every surviving string's carried
-    # matrix resident, so give the arena half of the free device memory (at most 64 GiB)
-    free, _ = torch.cuda.mem_get_info(0)
-    ctx = ctrace.TraceContext(tab, scratch_bytes=int(min(free // 2, 64 << 30)))
-    peaks = ctrace.ctr_probe_peaks(ctx.ctx)
-    offs, tau, op = pack(strings)
-    dev = "cuda:0"
-    d_offs = torch.from_numpy(offs).to(dev)
-    d_tau = torch.from_numpy(tau).to(dev)
-    d_op = torch.from_numpy(op).to(dev)
-    d_out = torch.zeros(n_cfg * ctrace.VALUE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
 
     kernel = {"auto": ctrace.CTR_KERNEL_AUTO, "wave": ctrace.CTR_KERNEL_WAVE, "block": ctrace.CTR_KERNEL_BLOCK,
-              "stream": ctrace.CTR_KERNEL_STREAM, "grouped": ctrace.CTR_KERNEL_GROUPED}[args.kernel]
-
-    def step(precision=ctrace.CTR_FP64, out_buf=None):
-        ctrace.ctr_trace_batch_device(ctx.ctx, n_cfg, d_offs.data_ptr(), d_tau.data_ptr(), d_op.data_ptr(),
-                                      (out_buf if out_buf is not None else d_out).data_ptr(), precision,
-                                      kernel if precision == ctrace.CTR_FP64 else ctrace.CTR_KERNEL_AUTO,
-                                      args.split_slices if precision == ctrace.CTR_FP32_SPLIT else 0)
-
+              "stream": ctrace.CTR_KERNEL_STREAM, "grouped": ctrace.CTR_KERNEL_GROUPED,
+              "grouped_rows": ctrace.CTR_KERNEL_GROUPED_ROWS}[args.kernel]
     if args.calib_copy_mib:
-        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctrace.ctr_kernel_timing(ctx.ctx, True)
-    ctrace.ctr_kernel_timing_read(ctx.ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    chain_ms, launches = ctrace.ctr_kernel_timing_read(ctx.ctx)
-    ctrace.ctr_kernel_timing(ctx.ctx, False)
-    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s; chain kernel {chain_ms / max(launches, 1):.3f} ms "
-          f"per launch over {launches} launches", file=sys.stderr, flush=True)
 
-    split = None
-    if not args.no_split:
-        # FP32-split leg: same batch, block products on FP32 MFMA over exact 8-bit slices
-        d_out_s = torch.zeros_like(d_out)
-        step(ctrace.CTR_FP32_SPLIT, d_out_s)
-        torch.cuda.synchronize()
-        ctrace.ctr_kernel_timing(ctx.ctx, True)
-        ctrace.ctr_kernel_timing_read(ctx.ctx)
-        ks = max(2, args.steps // 4)
-        ts = time.perf_counter()
-        for _ in range(ks):
-            step(ctrace.CTR_FP32_SPLIT, d_out_s)
-        torch.cuda.synchronize()
-        el_s = time.perf_counter() - ts
-        ms_s, n_s = ctrace.ctr_kernel_timing_read(ctx.ctx)
-        ctrace.ctr_kernel_timing(ctx.ctx, False)
-        outs = np.frombuffer(d_out_s.cpu().numpy().tobytes(), dtype=ctrace.VALUE_DTYPE)
-        rel_s, rel_a = [], []
-        for a, b in zip(outs, out):
-            if b["re"] == 0 and b["im"] == 0:
-                continue
-            M = max(a["log_scale"], b["log_scale"])
-            x = complex(a["re"], a["im"]) * math.exp(a["log_scale"] - M)
-            y = complex(b["re"], b["im"]) * math.exp(b["log_scale"] - M)
-            rel_s.append(abs(x - y) / abs(y))
-            rel_a.append(abs(x - y) / math.exp(b["log_abs"] - M))   # against the cancellation scale
-        rel_s = np.array(rel_s)
-        rel_a = np.array(rel_a)
-        split = {"value": n_cfg * ks / el_s, "unit": "trace evals/s", "steps": ks, "ms_per_step": el_s / ks * 1e3,
-                 "slice_bits": 8, "slices": args.split_slices,
-                 "fp32_products_per_fma": args.split_slices * (args.split_slices + 1) // 2,
-                 "launch_ms": ms_s / max(n_s, 1), "chain_ms_per_step": ms_s / ks,
-                 "rel_err_vs_fp64": {"p50": float(np.percentile(rel_s, 50)), "p99": float(np.percentile(rel_s, 99)),
-                                     "max": float(rel_s.max())} if rel_s.size else None,
-                 "err_vs_fp64_over_abs_sum": {"p50": float(np.percentile(rel_a, 50)),
-                                              "p99": float(np.percentile(rel_a, 99)),
-                                              "max": float(rel_a.max())} if rel_a.size else None}
+    def defaults(wl_id):
+        batch = args.batch if args.batch >= 0 else (200 if wl_id == 3 else 0)
+        split = args.split_configs if args.split_configs >= 0 else {1: 10_000, 2: 2000, 3: 16}[wl_id]
+        lazy = args.lazy_sample if args.lazy_sample >= 0 else (100 if wl_id == 3 else 10_000)
+        return batch, split, lazy
 
-    flops = algorithmic_flops(tab, strings)
-    if split is not None and split["chain_ms_per_step"] > 0:
-        per = flops / (split["chain_ms_per_step"] * 1e-3) / 1e12
-        split["achieved_fp64_equivalent_tflops"] = per
-        nprod = args.split_slices * (args.split_slices + 1) // 2
-        # the slice products the method needs (nprod FP32 products per FP64 multiply-add); the matrix
-        # pipe also runs the padding of the 16-column tiles, which only hardware counters see
-        split["needed_fp32_tflops"] = nprod * per
-        split["frac_fp32_peak"] = nprod * per / 157.3
-    per_launch_ms = chain_ms / max(launches, 1)
-    launches_per_step = launches / max(args.steps, 1)
-    achieved = flops / launches_per_step / (per_launch_ms * 1e-3) / 1e12 if per_launch_ms > 0 else None
-
-    lazy = None
-    if args.lazy_sample != 0:
-        lazy = lazy_leg(ctx, imp, strings[: args.lazy_sample] if args.lazy_sample > 0 else strings, out)
-
-    hist = None
-    if args.hist_sample != 0:
-        hist = histogram_leg(ctx, tab, imp, strings[: args.hist_sample] if args.hist_sample > 0 else strings)
-
-    markov = None
-    if args.mc_chains > 0:
-        markov = markov_leg(ctx, wl["impurity"], strings, args.mc_chains, args.mc_steps)
-        markov["full_traces"] = markov_leg(ctx, wl["impurity"], strings, args.mc_chains, args.mc_steps, True)
-
-    # single-configuration latency through the host-pointer entry point
-    lat = []
-    for s in strings[: args.latency_sample]:
-        t = time.perf_counter()
-        ctx.trace(s.tau, s.op)
-        lat.append((time.perf_counter() - t) * 1e3)
-    lat = np.array(lat)
-
-    cpu = None
-    rel = None
-    rel_dist = None
-    block_sparse = None
-    if not args.no_cpu:
-        sample = strings[: args.cpu_sample]
-        rate, done, el, threads, refs = cpu_baseline(imp, sample)
-        cpu = {"value": rate, "unit": "trace evals/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {done} of the {n_cfg} configurations, dense 2^10-dim FP64 chain, "
-                         f"{el:.1f} s"}
-        errs = []
-        for v, ref in zip(out[:done], refs):
-            if ref[0] == 0:
-                continue
-            g = complex(v["re"], v["im"])
-            M = max(v["log_scale"], ref[1])
-            a = g * math.exp(v["log_scale"] - M)
-            b = complex(ref[0]) * math.exp(ref[1] - M)
-            errs.append(abs(a - b) / abs(b))
-        rel = max(errs) if errs else None
-        rel_dist = {"p50": float(np.percentile(errs, 50)), "p99": float(np.percentile(errs, 99)),
-                    "max": float(max(errs)), "n": len(errs)} if errs else None
-        block_sparse = cpu_block_sparse(tab, strings)
-
-    value = n_cfg * args.steps / elapsed
-    xr = (tab.max_dim + 15) // 16 * 16
-    grouped_name = "k_gstep_wave" if xr <= (32 if tab.is_complex else 128) else "k_gstep"
-    kname = chain_kernel_name(tab, n_cfg) if args.kernel == "auto" else {
-        "wave": "k_chain_wave", "block": "k_chain", "stream": "k_chain_big",
-        "grouped": grouped_name}[args.kernel]
+    batch, split_n, lazy_n = defaults(args.workload)
+    name, rec = throughput_leg(args.workload, args.n_configs, batch, args.steps, args.warmup, kernel, split_n,
+                                  args.split_slices, lazy_n, args.no_cpu, True)
     line = {
         "metric": "trace evals/sec + MFMA % peak (FP32-split vs FP64) at <=1e-10 rel err; p50/p99",
-        "value": value,
+        "value": rec["value"],
         "unit": "trace evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": rec["dtype"],
         "data": "synthetic",
-        "config": {"workload": wl["name"] if not args.n_configs else f"{wl['name']} (first {n_cfg})",
-                   "impurity": wl["impurity"], "n_configs": n_cfg,
-                   "sectors": int(tab.n_sectors), "largest_block": int(tab.max_dim), "beta": tab.beta,
-                   "complex": bool(tab.is_complex), "precision": "FP64"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": measured_traffic(kname,
-                                                 wl["name"] if not args.n_configs else f"{wl['name']} (first {n_cfg})"),
-                     "kernel": kname, "algorithmic_flop_per_launch": flops / launches_per_step,
-                     "launch_ms": per_launch_ms},
-        "cpu_baseline": cpu,
-        "cpu_block_sparse": block_sparse,
-        "measured_peaks": peaks,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "entry": "ctr_trace (one configuration, host pointers)"},
-        "max_rel_err_vs_oracle_sample": rel,
-        "rel_err_vs_oracle_sample": rel_dist,
-        "fp32_split": split,
-        "lazy": lazy,
-        "histogram": hist,
-        "markov": markov,
+        "config": rec["config"],
+        "roofline": rec["roofline"],
+        "cpu_baseline": rec.get("cpu_baseline"),
+        "measured_peaks": rec["measured_peaks"],
+        "fp32_split": rec.get("fp32_split"),
+        "lazy": rec.get("lazy"),
         "paper_context": PAPER_CONTEXT,
     }
-    ctx.close()
-    if not args.no_also and args.workload == 1:
-        name, rec = fp64_throughput(2, 0, 3, 1)
-        line["also"] = {name: rec}
-        # the serving mix at one arrival rate, full grids (bench.py --serve for other settings)
+    for k in ("cpu_block_sparse", "rel_err_vs_oracle_sample"):
+        if k in rec:
+            line[k] = rec[k]
+    if not args.no_also:
+        also = {}
+        for wl_id in (1, 2):
+            if wl_id == args.workload:
+                continue
+            b, sp, lz = defaults(wl_id)
+            n, r = throughput_leg(wl_id, 0, b, 3, 1, ctrace.CTR_KERNEL_AUTO, sp, args.split_slices, lz,
+                                     args.no_cpu, False)
+            r.pop("measured_peaks", None)
+            also[n] = r
+        try:
+            also["dshell extras"] = dshell_extras(args)
+        except Exception as e:  # reported in the line; the measurements above stand
+            also["dshell extras"] = {"error": f"{type(e).__name__}: {e}"}
+        line["also"] = also
+        # the serving mix (bench.py --serve for other settings)
         sargs = argparse.Namespace(**{**vars(args), "serve_rate": 8000.0, "serve_seconds": 2.0,
                                       "serve_grid_share": "", "serve_cf": False})
         try:

@@ -91,11 +91,16 @@ enum {
   CTR_KERNEL_WAVE = 1,    /* one wavefront per 8-column panel; sectors <= 128 states, FP64 only */
   CTR_KERNEL_BLOCK = 2,   /* one workgroup per 16-column panel, X in LDS (<= 1024 real / 576 complex) */
   CTR_KERNEL_STREAM = 3,  /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
-  CTR_KERNEL_GROUPED = 4  /* block-grouped rounds: all strings of the batch advance one operator per
-                             round and the strings at the same block share one wide product; sectors
-                             <= 384 states, FP64; lazy calls reject by the string bounds before the
-                             rounds (no refinement while strings run).  Synchronises the stream once
-                             per batch (to size its scratch from the number of surviving strings) */
+  CTR_KERNEL_GROUPED = 4, /* block-grouped rounds: all strings of the batch advance one operator per
+                             round and the strings at the same block share one wide product; FP64;
+                             sectors <= 384 states keep every row of a block in one work item, larger
+                             ones take the row-chunked items of CTR_KERNEL_GROUPED_ROWS; lazy calls
+                             reject by the string bounds before the rounds (no refinement while strings
+                             run).  Synchronises the stream once per batch (to size its scratch from
+                             the number of surviving strings) */
+  CTR_KERNEL_GROUPED_ROWS = 5 /* the block-grouped rounds with work items of 64 columns x 128 rows of a
+                             block for any sector size: the per-column power of two is a device-wide
+                             maximum over the row chunks, applied when the next round loads the column */
 };
 
 typedef struct {
@@ -356,6 +361,14 @@ ctr_status ctr_strings(ctr_ctx *ctx, int32_t n_ops, const int32_t *op, int32_t *
  */
 ctr_status ctr_tune(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau, const int32_t *op,
                     int32_t *chosen, double *ms_per_kernel);
+
+/*
+ * The chain kernel (CTR_KERNEL_WAVE .. CTR_KERNEL_GROUPED_ROWS, never AUTO;
+ * 0 before any trace call) and the FP32-split slices (0 for FP64) of the last
+ * trace call on the context, as AUTO resolved them (for reports that name the
+ * kernel they time).  slices may be NULL.  Errors: CTR_ERR_ARG.
+ */
+ctr_status ctr_last_kernel(const ctr_ctx *ctx, int32_t *kernel, int32_t *slices);
 
 /* Wait for all work enqueued by the context. */
 ctr_status ctr_synchronize(ctr_ctx *ctx);

@@ -138,8 +138,10 @@ __global__ __launch_bounds__(1024) void k_gscan1(DevImp I, BatchArgs B, GroupArg
     G.info[1] = total;
     G.info[2] = s_max[0];  // rounds: the close of a string of n operators is round n - 1
     G.info[3] = s_cs[0];
-    // work items: at most one partial item per (round, group) on top of the full ones
-    G.info[4] = s_cs[0] / min(G.cw_step, G.cw_close) + s_ns[0] + 1;
+    // work items: at most one partial item per (round, group) on top of the full ones, times the
+    // row chunks of the largest block
+    const long long nrc = G.rchunk > 0 ? (I.xrows + G.rchunk - 1) / G.rchunk : 1;
+    G.info[4] = (s_cs[0] / min(G.cw_step, G.cw_close) + s_ns[0] + 1) * nrc;
   }
 }
 
@@ -187,10 +189,17 @@ __global__ __launch_bounds__(1024) void k_gsched(DevImp I, GroupArgs G) {
   const int* hcols = G.hcols + (long long)r * NK;
   int* gstart = G.gstart + (long long)r * (NK + 1);
   int* istart = G.istart + (long long)r * (NK + 1);
+  // items of group k: column tiles, times the row chunks of its block for products
+  auto items = [&](int k) {
+    const int cw = k < NB ? G.cw_step : G.cw_close;
+    int n = (hcols[k] + cw - 1) / cw;
+    if (k < NB && G.rchunk > 0 && n > 0) n *= (I.dim[I.next[k]] + G.rchunk - 1) / G.rchunk;
+    return n;
+  };
   int s1 = 0, s2 = 0;
   for (int k = lo; k < hi; ++k) {
     s1 += hist[k];
-    s2 += (hcols[k] + (k < NB ? G.cw_step : G.cw_close) - 1) / (k < NB ? G.cw_step : G.cw_close);
+    s2 += items(k);
   }
   int tot1 = 0, tot2 = 0;
   int run1 = block_exclusive_scan<int>(s1, s_tmp, &tot1);
@@ -199,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_gsched(DevImp I, GroupArgs G) {
     gstart[k] = run1;
     istart[k] = run2;
     run1 += hist[k];
-    run2 += (hcols[k] + (k < NB ? G.cw_step : G.cw_close) - 1) / (k < NB ? G.cw_step : G.cw_close);
+    run2 += items(k);
   }
   if (t == 0) {
     gstart[NK] = tot1;
@@ -365,6 +374,68 @@ __global__ __launch_bounds__(256) void k_gfirst(DevImp I, BatchArgs B, GroupArgs
       }
     }
     if (lane == 0) G.colexp[cb + j] = e;
+  }
+}
+
+// Round 0 for sectors of any size (row-chunked rounds): the column-scaled
+// copy of F is stored unscaled; its power of two is left pending for round 1.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_gfirst_big(DevImp I, BatchArgs B, GroupArgs G) {
+  const long long w = blockIdx.x;
+  if (w >= G.S) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = G.s_cfg[w];
+  const StrRec R = B.rec[(long long)c * I.n_sec + G.s_rec[w]];
+  const long long base = B.offsets[c];
+  const int n = (int)(B.offsets[c + 1] - base);
+  const long long cb = G.s_colbase[w];
+  const int s = R.q_start;
+  const double* e_s = I.esh + I.eoff[s];
+  if (n == 0) {
+    for (int j = threadIdx.x; j < R.width; j += 256) {
+      PanelRes o;
+      o.re = exp(-I.beta * e_s[j]);
+      o.im = 0.0;
+      o.e2 = 0.0;
+      G.colres[cb + j] = o;
+    }
+    return;
+  }
+  const double* tau = B.tau + base;
+  const int blk = s * I.nops + B.op[base + R.jstar];
+  const int s2 = I.next[blk];
+  const int d_out = I.dim[s2];
+  const int ld = (d_out + 15) & ~15;
+  const double* Fr = I.pool + I.boff[blk];
+  const double* Fi = Fr + (long long)ld * ((I.dim[s] + 3) & ~3);
+  const double dt0 = gap_before(tau, n, R.jstar, I.beta);
+  const double dt1 = gap_before(tau, n, (R.jstar + 1) % n, I.beta);
+  const double* e_2 = I.esh + I.eoff[s2];
+  const long long plane = G.T * (long long)I.xrows;
+  double* X = G.X[0];
+  for (int j = wave; j < R.width; j += 4) {
+    const double p0 = exp(-dt0 * e_s[j]);
+    double* col = X + (cb + j) * I.xrows;
+    double cm = 0.0;
+    for (int m = lane; m < ld; m += 64) {
+      const double p = m < d_out ? p0 * exp(-dt1 * e_2[m]) : 0.0;
+      const double vr = Fr[(long long)j * ld + m] * p;
+      col[m] = vr;
+      cm = fmax(cm, fabs(vr));
+      if (CPLX) {
+        const double vi = Fi[(long long)j * ld + m] * p;
+        col[plane + m] = vi;
+        cm = fmax(cm, fabs(vi));
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off));
+    int e = 0;
+    if (cm > 0.0) frexp(cm, &e);
+    if (lane == 0) {
+      G.colexp[cb + j] = 0;
+      G.epend[1 * G.T + cb + j] = cm > 0.0 ? e : kNoExp;
+      G.epend[2 * G.T + cb + j] = kNoExp;
+    }
   }
 }
 
@@ -597,6 +668,570 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
             const int m = tile * 16 + 4 * q + lq;
             col[m] = acc_r[i][t][q] * sc;
             if (CPLX) col[plane + m] = acc_i[i][t][q] * sc;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sectors of any size (beyond the register tile of k_gstep): a work item is
+// (group, CW-column tile, RB-row chunk), RB = WR * RT * 16 rows and
+// CW = WC * CT * 16 columns; wavefront (wr, wc) of the WR x WC grid computes RT
+// row tiles x CT column tiles.  The item's columns of X are staged through LDS
+// KC rows at a time, each scaled by its pending power of two as it is loaded
+// (exact); F comes from global memory with two k-steps of look-ahead.  The
+// epilogue applies the propagator of each column's next gap, stores the
+// products unscaled and takes the per-column maximum over the item's rows
+// (wavefront, then workgroup reduction), then one device-wide atomicMax per
+// column folds it into the round's pending exponent, which the next round
+// applies.  The row-chunk-0 item of every column tile also adds the pending
+// exponent it consumed to the column's accumulated one and clears the slot
+// of the round after next.  Closing strings take the diagonal of F * X from
+// the unscaled columns.
+template <bool CPLX, int WR, int WC, int RT, int CT>
+__global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, GroupArgs G, int r) {
+  constexpr int NW = WR * WC;
+  constexpr int NT = NW * 64;
+  constexpr int RB = WR * RT * 16;
+  constexpr int CW = WC * CT * 16;
+  constexpr int KC = 32;                 // rows of X staged in LDS per chunk
+  constexpr int LDB = KC + 1;            // odd stride: the 16 columns of a B fragment hit distinct banks
+  constexpr int PL = CPLX ? 2 : 1;
+  __shared__ double sB[PL * CW * LDB];
+  __shared__ double s_cmax[WR * CW];
+  __shared__ double s_dt[CW];
+  __shared__ double s_sc[CW];
+  __shared__ long long s_gcol[CW];
+  __shared__ int s_item;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WR, wc = wave / WR;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  const int XR = I.xrows;
+  const long long T = G.T;
+  const long long plane = T * (long long)XR;
+  const double* Xin = G.X[(r + 1) & 1];
+  double* Xout = G.X[r & 1];
+  const int* ep_in = G.epend + (long long)(r % 3) * T;
+  int* ep_out = G.epend + (long long)((r + 1) % 3) * T;
+  int* ep_clr = G.epend + (long long)((r + 2) % 3) * T;
+  const int* istart = G.istart + (long long)r * (NK + 1);
+  const int* gstart = G.gstart + (long long)r * (NK + 1);
+  const int* hcols = G.hcols + (long long)r * NK;
+  const int* colpref = G.colpref + (long long)r * G.S;
+  const long long* ritemoff = G.ritemoff;
+  typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+  const int n_items = G.n_items[r];
+  const int slot = blockIdx.x % kGroupCounters;
+  unsigned int* counter = G.counters + ((long long)r * kGroupCounters + slot) * 32;
+  for (;;) {
+    if (tid == 0) s_item = slot + kGroupCounters * (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= n_items) break;
+    const int key = G.item_key[ritemoff[r] + item];
+    const bool close = key >= NB;
+    const int blk = close ? key - NB : key;
+    const int s = blk / I.nops;
+    const int s2 = I.next[blk];
+    const int d_in = I.dim[s], d_out = I.dim[s2];
+    const int ld = (d_out + 15) & ~15;
+    const int kp = (d_in + 3) & ~3;
+    const double* Fr = I.pool + I.boff[blk];
+    const double* Fi = Fr + (long long)ld * kp;
+
+    if (close) {
+      // diagonal of F * X: column j of the string meets row j of F; the
+      // stored columns are unscaled, their power of two is colexp
+      const int cw = G.cw_close;
+      const int c0 = (item - istart[key]) * cw;
+      const int ncol = min(cw, hcols[key] - c0);
+      const long long relbase = G.rcoloff[r] + colpref[gstart[key]] + c0;
+      for (int j = wave; j < ncol; j += NW) {
+        const long long gcol = G.colg[relbase + j];
+        const int jj = (int)G.colaux[relbase + j];
+        const double* xr = Xin + gcol * XR;
+        double sr = 0.0, si = 0.0;
+        for (int k = lane; k < d_in; k += 64) {
+          const double fr = Fr[(long long)k * ld + jj], x = xr[k];
+          if (CPLX) {
+            const double fi = Fi[(long long)k * ld + jj], xi = xr[plane + k];
+            sr += fr * x - fi * xi;
+            si += fr * xi + fi * x;
+          } else {
+            sr += fr * x;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (lane == 0) {
+          PanelRes o;
+          o.re = sr;
+          o.im = si;
+          o.e2 = (double)G.colexp[gcol];
+          G.colres[gcol] = o;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    const int nrc = (d_out + RB - 1) / RB;
+    const int local = item - istart[key];
+    const int ct = local / nrc, rc = local - ct * nrc;
+    const int c0 = ct * CW;
+    const int ncol = min(CW, hcols[key] - c0);
+    const long long relbase = G.rcoloff[r] + colpref[gstart[key]] + c0;
+    if (tid < CW) {
+      const long long g = tid < ncol ? (long long)G.colg[relbase + tid] : -1;
+      const int pe = g >= 0 ? ep_in[g] : kNoExp;
+      s_gcol[tid] = g;
+      s_dt[tid] = tid < ncol ? G.colaux[relbase + tid] : 0.0;
+      s_sc[tid] = pe != kNoExp ? ldexp(1.0, -pe) : 1.0;
+      if (rc == 0 && g >= 0) {
+        if (pe != kNoExp) G.colexp[g] += pe;
+        ep_clr[g] = kNoExp;
+      }
+    }
+
+    dbl4 acc_r[RT][CT], acc_i[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        acc_r[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acc_i[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+      }
+    const int ntiles = ld >> 4;
+    const int tile0 = rc * (RB / 16) + wr * RT;  // first row tile of this wavefront
+    // A fragments run kPD k-steps ahead of the products (slot s % kPD)
+    constexpr int kPD = 2;
+    double rr[kPD][RT], ri[kPD][RT];
+#pragma unroll
+    for (int d = 0; d < kPD; ++d)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = tile0 + i;
+        rr[d][i] = ri[d][i] = 0.0;
+        if (tile < ntiles && 4 * d < kp) {
+          const long long a = (long long)(4 * d + lq) * ld + tile * 16 + ln;
+          rr[d][i] = Fr[a];
+          if (CPLX) ri[d][i] = Fi[a];
+        }
+      }
+    for (int k0 = 0; k0 < kp; k0 += KC) {
+      const int kc = min(KC, kp - k0);
+      __syncthreads();  // previous chunk consumed; column table visible
+      for (int idx = tid; idx < CW * kc; idx += NT) {
+        const int j = idx / kc, kk = idx - j * kc;
+        const long long g = s_gcol[j];
+        const long long a = g * XR + k0 + kk;
+        sB[j * LDB + kk] = g >= 0 ? Xin[a] * s_sc[j] : 0.0;
+        if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] * s_sc[j] : 0.0;
+      }
+      __syncthreads();
+      for (int kb = 0; kb < kc; kb += 4 * kPD) {
+#pragma unroll
+        for (int d = 0; d < kPD; ++d) {
+          const int kk = kb + 4 * d;
+          if (kk < kc) {
+            double ar[RT], ai[RT];
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+              ar[i] = rr[d][i];
+              ai[i] = ri[d][i];
+            }
+            const int kn = k0 + kk + 4 * kPD;
+            if (kn < kp) {
+#pragma unroll
+              for (int i = 0; i < RT; ++i) {
+                const int tile = tile0 + i;
+                if (tile < ntiles) {
+                  const long long a = (long long)(kn + lq) * ld + tile * 16 + ln;
+                  rr[d][i] = Fr[a];
+                  if (CPLX) ri[d][i] = Fi[a];
+                }
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+              const int jb = (wc * CT + t) * 16 + ln;
+              const double br = sB[jb * LDB + kk + lq];
+              const double bi = CPLX ? sB[CW * LDB + jb * LDB + kk + lq] : 0.0;
+#pragma unroll
+              for (int i = 0; i < RT; ++i) {
+                if (tile0 + i < ntiles) {
+                  acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, acc_r[i][t], 0, 0, 0);
+                  if (CPLX) {
+                    acc_r[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, acc_r[i][t], 0, 0, 0);
+                    acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, acc_i[i][t], 0, 0, 0);
+                    acc_i[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, acc_i[i][t], 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // epilogue: propagator of the next gap, per-column max over the item's rows
+    const double* e2 = I.esh + I.eoff[s2];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int j = (wc * CT + t) * 16 + ln;
+      const double dt = s_dt[j];
+      double cm = 0.0;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = tile0 + i;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * q + lq;
+            const double p = (m < d_out) ? exp(-dt * e2[m]) : 0.0;
+            acc_r[i][t][q] *= p;
+            cm = fmax(cm, fabs(acc_r[i][t][q]));
+            if (CPLX) {
+              acc_i[i][t][q] *= p;
+              cm = fmax(cm, fabs(acc_i[i][t][q]));
+            }
+          }
+        }
+      }
+      cm = fmax(cm, __shfl_xor(cm, 16));
+      cm = fmax(cm, __shfl_xor(cm, 32));
+      if (lq == 0) s_cmax[wr * CW + j] = cm;
+    }
+    __syncthreads();
+    if (tid < CW && s_gcol[tid] >= 0) {
+      double M = 0.0;
+      for (int w2 = 0; w2 < WR; ++w2) M = fmax(M, s_cmax[w2 * CW + tid]);
+      if (M > 0.0) {
+        int e = 0;
+        frexp(M, &e);
+        atomicMax(ep_out + s_gcol[tid], e);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int j = (wc * CT + t) * 16 + ln;
+      const long long g = s_gcol[j];
+      if (g < 0) continue;
+      double* col = Xout + g * XR;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = tile0 + i;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * q + lq;
+            col[m] = acc_r[i][t][q];
+            if (CPLX) col[plane + m] = acc_i[i][t][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+// FP32-split form of k_gbig (same items, staging, pending exponents and
+// closes).  Each FP64 product is formed from NSL integer slices of 8 bits per
+// operand: F per row, scaled by the row's power of two (rexp) so that |F| < 1;
+// X per column, scaled into (-1, 1) by its pending power of two.  With
+//   f = sum_s A_s 2^{-8 s},  x = sum_t B_t 2^{-8 t},  |A_s|, |B_t| <= 255,
+// the slice products with s + t <= NSL + 1 run on FP32 MFMA 16x16x4 and are
+// summed per level L = s + t; a level gets at most NSL (2 NSL complex)
+// products below 2^16 per value of k, so over kSplitK values of k its FP32
+// sum stays an integer below 2^24 and is exact.  After every such chunk the
+// level sums are converted to FP64 and added with weight 2^{-8 L}.  The
+// propagators, the rescale and the closes stay FP64.
+template <bool CPLX, int NSL>
+__host__ __device__ constexpr int split_k() {
+  return ((1 << 8) / (NSL * (CPLX ? 2 : 1))) & ~3;
+}
+
+template <int NSL>
+__device__ __forceinline__ void cut_slices(double v, float* d) {
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    v *= 256.0;
+    const double a = trunc(v);
+    d[s] = (float)a;
+    v -= a;
+  }
+}
+
+template <bool CPLX, int WR, int WC, int RT, int CT, int NSL>
+__global__ __launch_bounds__(WR * WC * 64) void k_gbig_split(DevImp I, BatchArgs B, GroupArgs G, int r) {
+  constexpr int NW = WR * WC;
+  constexpr int NT = NW * 64;
+  constexpr int RB = WR * RT * 16;
+  constexpr int CW = WC * CT * 16;
+  constexpr int KC = 32;
+  constexpr int LDB = KC + 1;
+  constexpr int PL = CPLX ? 2 : 1;
+  constexpr int KS = split_k<CPLX, NSL>();  // values of k per exact FP32 chunk (a multiple of 4)
+  static_assert(KC % KS == 0 || KS % 4 == 0, "chunking");
+  __shared__ double sB[PL * CW * LDB];
+  __shared__ double s_cmax[WR * CW];
+  __shared__ double s_dt[CW];
+  __shared__ double s_sc[CW];
+  __shared__ long long s_gcol[CW];
+  __shared__ int s_item;
+  typedef double dbl4 __attribute__((ext_vector_type(4)));
+  typedef float flt4 __attribute__((ext_vector_type(4)));
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WR, wc = wave / WR;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int NB = I.n_sec * I.nops, NK = 2 * NB;
+  const int XR = I.xrows;
+  const long long T = G.T;
+  const long long plane = T * (long long)XR;
+  const double* Xin = G.X[(r + 1) & 1];
+  double* Xout = G.X[r & 1];
+  const int* ep_in = G.epend + (long long)(r % 3) * T;
+  int* ep_out = G.epend + (long long)((r + 1) % 3) * T;
+  int* ep_clr = G.epend + (long long)((r + 2) % 3) * T;
+  const int* istart = G.istart + (long long)r * (NK + 1);
+  const int* gstart = G.gstart + (long long)r * (NK + 1);
+  const int* hcols = G.hcols + (long long)r * NK;
+  const int* colpref = G.colpref + (long long)r * G.S;
+  const long long* ritemoff = G.ritemoff;
+
+  const int n_items = G.n_items[r];
+  const int slot = blockIdx.x % kGroupCounters;
+  unsigned int* counter = G.counters + ((long long)r * kGroupCounters + slot) * 32;
+  for (;;) {
+    if (tid == 0) s_item = slot + kGroupCounters * (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= n_items) break;
+    const int key = G.item_key[ritemoff[r] + item];
+    const bool close = key >= NB;
+    const int blk = close ? key - NB : key;
+    const int s = blk / I.nops;
+    const int s2 = I.next[blk];
+    const int d_in = I.dim[s], d_out = I.dim[s2];
+    const int ld = (d_out + 15) & ~15;
+    const int kp = (d_in + 3) & ~3;
+    const double* Fr = I.pool + I.boff[blk];
+    const double* Fi = Fr + (long long)ld * kp;
+
+    if (close) {
+      const int cw = G.cw_close;
+      const int c0 = (item - istart[key]) * cw;
+      const int ncol = min(cw, hcols[key] - c0);
+      const long long relbase = G.rcoloff[r] + colpref[gstart[key]] + c0;
+      for (int j = wave; j < ncol; j += NW) {
+        const long long gcol = G.colg[relbase + j];
+        const int jj = (int)G.colaux[relbase + j];
+        const double* xr = Xin + gcol * XR;
+        double sr = 0.0, si = 0.0;
+        for (int k = lane; k < d_in; k += 64) {
+          const double fr = Fr[(long long)k * ld + jj], x = xr[k];
+          if (CPLX) {
+            const double fi = Fi[(long long)k * ld + jj], xi = xr[plane + k];
+            sr += fr * x - fi * xi;
+            si += fr * xi + fi * x;
+          } else {
+            sr += fr * x;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (lane == 0) {
+          PanelRes o;
+          o.re = sr;
+          o.im = si;
+          o.e2 = (double)G.colexp[gcol];
+          G.colres[gcol] = o;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    const int nrc = (d_out + RB - 1) / RB;
+    const int local = item - istart[key];
+    const int ct = local / nrc, rc = local - ct * nrc;
+    const int c0 = ct * CW;
+    const int ncol = min(CW, hcols[key] - c0);
+    const long long relbase = G.rcoloff[r] + colpref[gstart[key]] + c0;
+    if (tid < CW) {
+      const long long g = tid < ncol ? (long long)G.colg[relbase + tid] : -1;
+      const int pe = g >= 0 ? ep_in[g] : kNoExp;
+      s_gcol[tid] = g;
+      s_dt[tid] = tid < ncol ? G.colaux[relbase + tid] : 0.0;
+      s_sc[tid] = pe != kNoExp ? ldexp(1.0, -pe) : 1.0;
+      if (rc == 0 && g >= 0) {
+        if (pe != kNoExp) G.colexp[g] += pe;
+        ep_clr[g] = kNoExp;
+      }
+    }
+    const short* rex = I.rexp + I.roff[blk];
+    const int ntiles = ld >> 4;
+    const int tile0 = rc * (RB / 16) + wr * RT;
+    // inverse row scales of the A rows this lane feeds (row tile*16 + ln)
+    double ainv[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ainv[i] = (tile0 + i < ntiles) ? ldexp(1.0, -(int)rex[(tile0 + i) * 16 + ln]) : 0.0;
+
+    dbl4 acc_r[RT][CT], acc_i[RT][CT];
+    flt4 lr[RT][CT][NSL], li[RT][CT][NSL];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        acc_r[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acc_i[i][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int L = 0; L < NSL; ++L) {
+          lr[i][t][L] = flt4{0.f, 0.f, 0.f, 0.f};
+          li[i][t][L] = flt4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    int in_chunk = 0;  // values of k summed into the FP32 levels since the last flush
+    for (int k0 = 0; k0 < kp; k0 += KC) {
+      const int kc = min(KC, kp - k0);
+      __syncthreads();
+      for (int idx = tid; idx < CW * kc; idx += NT) {
+        const int j = idx / kc, kk = idx - j * kc;
+        const long long g = s_gcol[j];
+        const long long a = g * XR + k0 + kk;
+        sB[j * LDB + kk] = g >= 0 ? Xin[a] * s_sc[j] : 0.0;
+        if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] * s_sc[j] : 0.0;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < kc; kk += 4) {
+        float afr[RT][NSL], afi[RT][NSL];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const int tile = tile0 + i;
+          double vr = 0.0, vi = 0.0;
+          if (tile < ntiles) {
+            const long long a = (long long)(k0 + kk + lq) * ld + tile * 16 + ln;
+            vr = Fr[a] * ainv[i];
+            if (CPLX) vi = Fi[a] * ainv[i];
+          }
+          cut_slices<NSL>(vr, afr[i]);
+          if (CPLX) cut_slices<NSL>(vi, afi[i]);
+        }
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+          const int jb = (wc * CT + t) * 16 + ln;
+          float bxr[NSL], bxi[NSL];
+          cut_slices<NSL>(sB[jb * LDB + kk + lq], bxr);
+          if (CPLX) cut_slices<NSL>(sB[CW * LDB + jb * LDB + kk + lq], bxi);
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            if (tile0 + i < ntiles) {
+              // level L = s + t (slice indices from 1), kept for L <= NSL + 1
+#pragma unroll
+              for (int L = 2; L <= NSL + 1; ++L) {
+#pragma unroll
+                for (int s1 = 1; s1 < L; ++s1) {
+                  const int t1 = L - s1;
+                  lr[i][t][L - 2] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(afr[i][s1 - 1], bxr[t1 - 1], lr[i][t][L - 2], 0, 0, 0);
+                  if (CPLX) {
+                    lr[i][t][L - 2] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(-afi[i][s1 - 1], bxi[t1 - 1], lr[i][t][L - 2], 0, 0, 0);
+                    li[i][t][L - 2] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(afr[i][s1 - 1], bxi[t1 - 1], li[i][t][L - 2], 0, 0, 0);
+                    li[i][t][L - 2] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(afi[i][s1 - 1], bxr[t1 - 1], li[i][t][L - 2], 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
+        }
+        in_chunk += 4;
+        if (in_chunk == KS || k0 + kk + 4 >= kp) {
+          // exact FP32 level sums -> FP64 with weights 2^{-8 L}
+#pragma unroll
+          for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+#pragma unroll
+              for (int L = 2; L <= NSL + 1; ++L) {
+                const double wgt = ldexp(1.0, -8 * L);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  acc_r[i][t][q] += (double)lr[i][t][L - 2][q] * wgt;
+                  if (CPLX) acc_i[i][t][q] += (double)li[i][t][L - 2][q] * wgt;
+                }
+                lr[i][t][L - 2] = flt4{0.f, 0.f, 0.f, 0.f};
+                li[i][t][L - 2] = flt4{0.f, 0.f, 0.f, 0.f};
+              }
+          in_chunk = 0;
+        }
+      }
+    }
+
+    // epilogue: row scales back, propagator of the next gap, per-column max;
+    // item q of lane l in the FP32 result is row 4 (l / 16) + q, column l % 16
+    const double* e2 = I.esh + I.eoff[s2];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int j = (wc * CT + t) * 16 + ln;
+      const double dt = s_dt[j];
+      double cm = 0.0;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = tile0 + i;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * lq + q;
+            const double p = (m < d_out) ? ldexp(exp(-dt * e2[m]), (int)rex[m]) : 0.0;
+            acc_r[i][t][q] *= p;
+            cm = fmax(cm, fabs(acc_r[i][t][q]));
+            if (CPLX) {
+              acc_i[i][t][q] *= p;
+              cm = fmax(cm, fabs(acc_i[i][t][q]));
+            }
+          }
+        }
+      }
+      cm = fmax(cm, __shfl_xor(cm, 16));
+      cm = fmax(cm, __shfl_xor(cm, 32));
+      if (lq == 0) s_cmax[wr * CW + j] = cm;
+    }
+    __syncthreads();
+    if (tid < CW && s_gcol[tid] >= 0) {
+      double M = 0.0;
+      for (int w2 = 0; w2 < WR; ++w2) M = fmax(M, s_cmax[w2 * CW + tid]);
+      if (M > 0.0) {
+        int e = 0;
+        frexp(M, &e);
+        atomicMax(ep_out + s_gcol[tid], e);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int j = (wc * CT + t) * 16 + ln;
+      const long long g = s_gcol[j];
+      if (g < 0) continue;
+      double* col = Xout + g * XR;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int tile = tile0 + i;
+        if (tile < ntiles) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = tile * 16 + 4 * lq + q;
+            col[m] = acc_r[i][t][q];
+            if (CPLX) col[plane + m] = acc_i[i][t][q];
           }
         }
       }
@@ -906,44 +1541,73 @@ namespace {
 struct GVariant {
   const void* fn;
   int nw, cw;
+  int rchunk;  // rows per product item (0: all rows)
 };
 
 template <bool CPLX, int NW, int RT, int CT>
 GVariant make_gvariant() {
-  return GVariant{reinterpret_cast<const void*>(&k_gstep<CPLX, NW, RT, CT>), NW, CT * 16};
+  return GVariant{reinterpret_cast<const void*>(&k_gstep<CPLX, NW, RT, CT>), NW, CT * 16, 0};
 }
 
 template <bool CPLX, int MT, int CT = 1>
 GVariant make_wvariant() {
-  return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT, CT>), 4, 16 * CT};
+  return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT, CT>), 4, 16 * CT, 0};
+}
+
+template <bool CPLX, int WR, int WC, int RT, int CT>
+GVariant make_bvariant() {
+  return GVariant{reinterpret_cast<const void*>(&k_gbig<CPLX, WR, WC, RT, CT>), WR * WC, WC * CT * 16, WR * RT * 16};
+}
+
+template <bool CPLX, int NSL>
+GVariant make_svariant() {
+  constexpr int WR = 4, WC = 2, RT = 1, CT = 2;
+  return GVariant{reinterpret_cast<const void*>(&k_gbig_split<CPLX, WR, WC, RT, CT, NSL>), WR * WC, WC * CT * 16,
+                  WR * RT * 16};
 }
 
 // Small sectors: one wavefront per item of 16 or 32 columns (all row tiles
-// in registers); larger ones: a workgroup per 32/64-column item, rows split
-// over its wavefronts.  alt = 1 selects the other measured tile shape where
-// there is one (the autotuner times both); false if there is none.
-bool pick_gvariant(const DevImp& imp, int alt, GVariant* v) {
+// in registers); up to 384 rows: a workgroup per 32/64-column item, rows split
+// over its wavefronts; larger: row-chunked items (k_gbig).  alt = 1 selects
+// the other measured tile shape where there is one (the autotuner times
+// both); false if there is none.  alt = 2, 3: the row-chunked shapes at any
+// size.
+bool pick_gvariant(const DevImp& imp, int alt, GVariant* v, int split = 0) {
   const int tiles = imp.xrows / 16;
+  if (split) {
+    // FP32-split products: row-chunked items only (6 or 7 slices)
+    if (split != 6 && split != 7) return false;
+    if (imp.is_complex) *v = split == 7 ? make_svariant<true, 7>() : make_svariant<true, 6>();
+    else *v = split == 7 ? make_svariant<false, 7>() : make_svariant<false, 6>();
+    return alt == 2;
+  }
+  if (alt >= 2) {
+    // row-chunked items at any size (alt 2 and 3: the two tile shapes)
+    if (imp.is_complex) *v = alt == 3 ? make_bvariant<true, 4, 1, 2, 4>() : make_bvariant<true, 4, 2, 2, 2>();
+    else *v = alt == 3 ? make_bvariant<false, 4, 1, 2, 4>() : make_bvariant<false, 4, 2, 2, 2>();
+    return alt <= 3;
+  }
   if (imp.is_complex) {
     if (tiles <= 2) *v = make_wvariant<true, 2>();
     else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
     else if (tiles <= 24) *v = alt ? make_gvariant<true, 8, 3, 2>() : make_gvariant<true, 12, 2, 2>();
-    else return false;
-    return !alt || (tiles > 8 && tiles <= 24);
+    else *v = alt ? make_bvariant<true, 4, 1, 2, 4>() : make_bvariant<true, 4, 2, 2, 2>();
+    return !alt || tiles > 8;
   }
   if (tiles <= 2) *v = make_wvariant<false, 2>();
   else if (tiles <= 4) *v = make_wvariant<false, 4>();
   else if (tiles <= 8) *v = alt ? make_wvariant<false, 8, 1>() : make_wvariant<false, 8, 2>();
   else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
-  else return false;
-  return !alt || (tiles > 4 && tiles <= 8);
+  else *v = alt ? make_bvariant<false, 4, 1, 2, 4>() : make_bvariant<false, 4, 2, 2, 2>();
+  return !alt || (tiles > 4 && tiles <= 8) || tiles > 24;
 }
 
 }  // namespace
 
-int group_grid(const DevImp& imp, int device, int alt, int* cw_step) {
+int group_grid(const DevImp& imp, int device, int alt, int* cw_step, int* rchunk_out, int split) {
   GVariant v;
-  if (!pick_gvariant(imp, alt, &v)) return 0;
+  if (!pick_gvariant(imp, alt, &v, split)) return 0;
+  if (rchunk_out) *rchunk_out = v.rchunk;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.nw * 64, 0) != hipSuccess) return 0;
   int cus = 0;
@@ -975,19 +1639,25 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
     if (ns > 0) hipLaunchKernelGGL(k_gitems, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, stream, imp, b, g);
   }
   if (g.S > 0) {
-    if (imp.is_complex)
+    if (g.rchunk > 0) {
+      if (imp.is_complex)
+        hipLaunchKernelGGL(k_gfirst_big<true>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
+      else
+        hipLaunchKernelGGL(k_gfirst_big<false>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
+    } else if (imp.is_complex) {
       hipLaunchKernelGGL(k_gfirst<true>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
-    else
+    } else {
       hipLaunchKernelGGL(k_gfirst<false>, dim3((unsigned)g.S), dim3(256), 0, stream, imp, b, g);
+    }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
-                              hipStream_t stream) {
+                              int split, hipStream_t stream) {
   GVariant v;
-  if (!pick_gvariant(imp, alt, &v) || grid <= 0) return hipErrorInvalidValue;
-  if (v.cw != g.cw_step) return hipErrorInvalidValue;  // the schedule was built for another item width
+  if (!pick_gvariant(imp, alt, &v, split) || grid <= 0) return hipErrorInvalidValue;
+  if (v.cw != g.cw_step || v.rchunk != g.rchunk) return hipErrorInvalidValue;  // schedule built for another shape
   void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b), const_cast<GroupArgs*>(&g), &r};
   return hipLaunchKernel(v.fn, dim3(grid), dim3(v.nw * 64), args, 0, stream);
 }

@@ -38,6 +38,14 @@ struct ctr_ctx {
   int grid_big = 0;   // streaming kernel
   int grid_group = 0;  // block-grouped rounds, 0 = not applicable
   int cw_group = 0;    // columns per grouped work item
+  int rc_group = 0;    // rows per grouped product item (0: all rows of the block)
+  int grid_rows = 0;   // the row-chunked grouped rounds (CTR_KERNEL_GROUPED_ROWS), any sector size
+  int cw_rows = 0, rc_rows = 0;
+  int grid_rsplit[2] = {0, 0};  // their FP32-split form, 6 and 7 slices
+  int cw_rsplit = 0, rc_rsplit = 0;
+  int last_kernel = 0, last_slices = 0;  // chain kernel and precision of the last trace call
+  bool rows = false;   // the current grouped call runs the row-chunked items
+  int gsplit = 0;      // slices of the current grouped call's FP32-split products (0: FP64)
   int galt = 0;        // grouped tile shape: 0 default, 1 the alternative (picked by ctr_tune)
   int tuned = 0;       // CTR_KERNEL_* picked by ctr_tune for FP64 batches (0 = none)
   int tuned_min_batch = 0;
@@ -155,8 +163,9 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
   g.info = (long long*)b.take(8 * sizeof(long long));
   if (!g.s_cfg || !g.s_rec || !g.s_width || !g.s_n || !g.s_colbase || !g.info)
     return fail(ctx, CTR_ERR_OOM, "arena too small");
-  g.cw_step = ctx->cw_group;
+  g.cw_step = ctx->gsplit ? ctx->cw_rsplit : ctx->rows ? ctx->cw_rows : ctx->cw_group;
   g.cw_close = ctr::kGroupCloseCols;
+  g.rchunk = ctx->gsplit ? ctx->rc_rsplit : ctx->rows ? ctx->rc_rows : ctx->rc_group;
   if ((e = ctr::launch_group_prepare(ctx->imp, a, g, max_s, ctx->stream)) != hipSuccess)
     return hip_fail(ctx, e, "grouped prepare kernels");
   long long info[5] = {0, 0, 0, 0, 0};
@@ -191,9 +200,10 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
   g.item_key = (int*)b.take((size_t)std::max(g.NI, 1LL) * sizeof(int));
   g.colg = (int*)b.take((size_t)std::max(g.CS, 1LL) * sizeof(int));
   g.colaux = (double*)b.take((size_t)std::max(g.CS, 1LL) * sizeof(double));
+  g.epend = g.rchunk > 0 ? (int*)b.take((size_t)3 * std::max(g.T, 1LL) * sizeof(int)) : nullptr;
   if (!g.hist || !g.hcols || !g.cursor || !g.gstart || !g.istart || !g.n_items || !g.counters || !g.sorted ||
       !g.colpref || !g.X[0] || !g.X[1] || !g.colexp || !g.colres || !g.rcols || !g.rcoloff || !g.ritemoff ||
-      !g.item_key || !g.colg || !g.colaux)
+      !g.item_key || !g.colg || !g.colaux || (g.rchunk > 0 && !g.epend))
     return fail(ctx, CTR_ERR_OOM, "arena too small for the grouped rounds");
   HIP_TRY(ctx, hipMemsetAsync(g.rcols, 0, (size_t)R * sizeof(long long), ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(g.n_items, 0, (size_t)R * sizeof(int), ctx->stream));
@@ -204,6 +214,8 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
   HIP_TRY(ctx, hipMemsetAsync(g.colres, 0, (size_t)std::max(g.T, 1LL) * sizeof(PanelRes), ctx->stream));
   if ((e = ctr::launch_group_schedule(ctx->imp, a, g, ctx->stream)) != hipSuccess)
     return hip_fail(ctx, e, "grouped schedule kernels");
+  ctx->last_kernel = g.rchunk > 0 ? CTR_KERNEL_GROUPED_ROWS : CTR_KERNEL_GROUPED;
+  ctx->last_slices = ctx->gsplit;
   for (int r = 1; r < g.R; ++r) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (ctx->timing) {
@@ -211,8 +223,9 @@ ctr_status enqueue_grouped(ctr_ctx* ctx, BatchArgs& a, Bump& b, const ctr::HistA
       HIP_TRY(ctx, hipEventCreate(&t1));
       HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
     }
-    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, shared_grid(ctx, ctx->grid_group, ctr::kGroupCounters), ctx->galt,
-                                       ctx->stream)) != hipSuccess)
+    const int grid = ctx->gsplit ? ctx->grid_rsplit[ctx->gsplit == 7] : ctx->rows ? ctx->grid_rows : ctx->grid_group;
+    if ((e = ctr::launch_group_round(ctx->imp, a, g, r, shared_grid(ctx, grid, ctr::kGroupCounters),
+                                     ctx->rows || ctx->gsplit ? 2 : ctx->galt, ctx->gsplit, ctx->stream)) != hipSuccess)
       return hip_fail(ctx, e, "grouped round kernel");
     if (ctx->timing) {
       HIP_TRY(ctx, hipEventRecord(t1, ctx->stream));
@@ -245,6 +258,8 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
     HIP_TRY(ctx, hipEventCreate(&t1));
     HIP_TRY(ctx, hipEventRecord(t0, ctx->stream));
   }
+  ctx->last_kernel = kind == Kernel::Wave ? CTR_KERNEL_WAVE : kind == Kernel::Block ? CTR_KERNEL_BLOCK : CTR_KERNEL_STREAM;
+  ctx->last_slices = split ? ctx->slices : 0;
   switch (kind) {
     case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, shared_grid(ctx, ctx->grid_wave, 1), ctx->stream); break;
     case Kernel::Block:
@@ -296,10 +311,14 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       return fail(ctx, CTR_ERR_ARG, "unknown precision");
     }
     want = opts->kernel;
-    if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_GROUPED) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
+    if (want < CTR_KERNEL_AUTO || want > CTR_KERNEL_GROUPED_ROWS) return fail(ctx, CTR_ERR_ARG, "unknown kernel");
   }
+  ctx->rows = false;
+  ctx->gsplit = 0;
   // grouped rounds with a threshold: the plan's bound rejects, strings are not refined while they run
   const bool group_ok = !*split && ctx->grid_group > 0;
+  // FP32-split products in grouped rounds: the row-chunked items
+  const bool rsplit_ok = *split && ctx->grid_rsplit[ctx->slices == 7] > 0;
   const bool wave_ok = !*split && ctx->grid_wave > 0;
   const bool block_ok = (*split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid) > 0;
   const bool stream_ok = !*split && ctx->grid_big > 0;
@@ -314,7 +333,10 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       }
       // sectors <= 128 states: the per-string wavefront kernel is as fast as
       // the grouped rounds; above, the grouped rounds win on batches
-      if (wave_ok) *kind = Kernel::Wave;
+      if (rsplit_ok && (n_cfg >= kGroupMinBatch || !block_ok)) {
+        ctx->gsplit = ctx->slices;
+        *kind = Kernel::Group;
+      } else if (wave_ok) *kind = Kernel::Wave;
       else if (group_ok && n_cfg >= kGroupMinBatch) *kind = Kernel::Group;
       else if (block_ok) *kind = Kernel::Block;
       else if (stream_ok) *kind = Kernel::Stream;
@@ -332,8 +354,18 @@ ctr_status check_opts(ctr_ctx* ctx, const ctr_opts* opts, bool* split, Kernel* k
       if (!stream_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "streaming kernel runs FP64 only");
       *kind = Kernel::Stream;
       return CTR_OK;
+    case CTR_KERNEL_GROUPED_ROWS:
     default:
-      if (!group_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "grouped rounds need FP64 and sectors <= 384 states");
+      // FP32-split grouped calls run the row-chunked items
+      if (*split) {
+        if (!rsplit_ok) return fail(ctx, CTR_ERR_UNSUPPORTED, "no grouped FP32-split kernel for this impurity");
+        ctx->gsplit = ctx->slices;
+      } else if (want == CTR_KERNEL_GROUPED_ROWS) {
+        if (ctx->grid_rows <= 0) return fail(ctx, CTR_ERR_UNSUPPORTED, "row-chunked rounds do not fit the device");
+        ctx->rows = true;
+      } else if (!group_ok) {
+        return fail(ctx, CTR_ERR_UNSUPPORTED, "grouped rounds do not fit the device");
+      }
       *kind = Kernel::Group;
       return CTR_OK;
   }
@@ -716,8 +748,12 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
   ctx->cw_group = 0;
+  ctx->rc_group = 0;
   ctx->galt = 0;
-  ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, 0, &ctx->cw_group);
+  ctx->grid_group = ctr::group_grid(ctx->imp, ctx->device, 0, &ctx->cw_group, &ctx->rc_group);
+  ctx->grid_rows = ctr::group_grid(ctx->imp, ctx->device, 2, &ctx->cw_rows, &ctx->rc_rows);
+  ctx->grid_rsplit[0] = ctr::group_grid(ctx->imp, ctx->device, 2, &ctx->cw_rsplit, &ctx->rc_rsplit, 6);
+  ctx->grid_rsplit[1] = ctr::group_grid(ctx->imp, ctx->device, 2, &ctx->cw_rsplit, &ctx->rc_rsplit, 7);
   ctx->tuned = 0;
   ctx->tuned_min_batch = 0;
   ctx->xbuf = nullptr;
@@ -757,29 +793,31 @@ ctr_status ctr_tune(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const d
                            {CTR_KERNEL_GROUPED, 0}, {CTR_KERNEL_GROUPED, 1}};
   int best = 0, g_alt = 0;
   double best_ms = 0.0, g_ms = -1.0;
-  const int grid0 = ctx->grid_group, cw0 = ctx->cw_group;
+  const int grid0 = ctx->grid_group, cw0 = ctx->cw_group, rc0 = ctx->rc_group;
   // an error return leaves the grouped rounds in their default tile shape
   struct Restore {
     ctr_ctx* c;
-    int grid, cw;
+    int grid, cw, rc;
     bool keep = false;
     ~Restore() {
       if (!keep) {
         c->galt = 0;
         c->grid_group = grid;
         c->cw_group = cw;
+        c->rc_group = rc;
       }
     }
-  } restore{ctx, grid0, cw0};
+  } restore{ctx, grid0, cw0, rc0};
   for (const auto& cand : cands) {
     const int want = cand[0], alt = cand[1];
     if (want == CTR_KERNEL_GROUPED) {
-      int cw = 0;
-      const int grid = ctr::group_grid(ctx->imp, ctx->device, alt, &cw);
+      int cw = 0, rc = 0;
+      const int grid = ctr::group_grid(ctx->imp, ctx->device, alt, &cw, &rc);
       if (grid <= 0) continue;
       ctx->galt = alt;
       ctx->grid_group = grid;
       ctx->cw_group = cw;
+      ctx->rc_group = rc;
     }
     ctr_opts o{};
     o.kernel = want;
@@ -815,8 +853,11 @@ ctr_status ctr_tune(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const d
   }
   // the grouped rounds keep their fastest tile shape
   ctx->galt = g_alt;
-  ctx->grid_group = ctx->galt ? ctr::group_grid(ctx->imp, ctx->device, 1, &ctx->cw_group) : grid0;
-  if (!ctx->galt) ctx->cw_group = cw0;
+  ctx->grid_group = ctx->galt ? ctr::group_grid(ctx->imp, ctx->device, 1, &ctx->cw_group, &ctx->rc_group) : grid0;
+  if (!ctx->galt) {
+    ctx->cw_group = cw0;
+    ctx->rc_group = rc0;
+  }
   restore.keep = true;
   ctx->err.clear();
   if (!best) return fail(ctx, CTR_ERR_UNSUPPORTED, "no chain kernel ran the sample");
@@ -971,6 +1012,13 @@ ctr_status ctr_kernel_timing_read(ctr_ctx* ctx, double* total_ms, int32_t* n_lau
   *total_ms = sum;
   *n_launches = (int32_t)ctx->events.size();
   ctx->events.clear();
+  return CTR_OK;
+}
+
+ctr_status ctr_last_kernel(const ctr_ctx* ctx, int32_t* kernel, int32_t* slices) {
+  if (!ctx || !kernel) return CTR_ERR_ARG;
+  *kernel = ctx->last_kernel;
+  if (slices) *slices = ctx->last_slices;
   return CTR_OK;
 }
 

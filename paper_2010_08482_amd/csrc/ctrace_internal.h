@@ -127,7 +127,15 @@ struct GroupArgs {
   double* X[2];                // carried matrices, ping-pong: column g at g * xrows (imaginary plane at + T * xrows)
   int* colexp;                 // [T] accumulated power of two of every column
   PanelRes* colres;            // [T] closed column values
+  // Sectors beyond one workgroup's register tile: product items cover rchunk
+  // rows of the block (0 = all rows).  The per-column power of two of a round
+  // is then a device-wide integer maximum over the row chunks, kept pending in
+  // epend[(r + 1) % 3] (unscaled values stored) and applied by the loads of
+  // round r + 1; round r resets epend[(r + 2) % 3] for the rounds after.
+  int rchunk;
+  int* epend;                  // [3][T] pending exponents, kNoExp = none
 };
+constexpr int kNoExp = -(1 << 20);
 
 // Label histogram of a batch (ctrace_hist.hip), after the combine kernel.
 // The values of string (c, q0) with record R are vals[colbase[cfg_off[c] +
@@ -161,14 +169,16 @@ constexpr int kWavePanelHost = 8;
 int big_grid(const DevImp& imp, int device, size_t* lds_bytes);
 size_t big_xbuf_doubles(const DevImp& imp, int grid);
 hipError_t launch_chain_big(const DevImp& imp, const BatchArgs& b, double* xbuf, int grid, hipStream_t stream);
-// Block-grouped path (sectors of at most 384 states); grid 0 = not applicable.
+// Block-grouped path; grid 0 = not applicable.  rchunk_out (may be null) gets
+// the rows per product item of the chosen shape (0 = every row in one item).
 // alt = 1: the alternative tile shape (grid 0 when there is none for this impurity).
-int group_grid(const DevImp& imp, int device, int alt, int* cw_step);
+// split: 0 FP64 products, 6 or 7 the FP32-split row-chunked items (alt 2 only).
+int group_grid(const DevImp& imp, int device, int alt, int* cw_step, int* rchunk_out = nullptr, int split = 0);
 hipError_t launch_group_prepare(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, long long max_strings,
                                 hipStream_t stream);
 hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
-                              hipStream_t stream);
+                              int split, hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
 // Peak-rate probe (ctrace_probe.hip): out[0..4] = FP64 16x16x4 and 4x4x4 MFMA and FP32 16x16x4
 // MFMA TFLOP/s, clock (MHz), compute units.  sink: 256 doubles of device memory.

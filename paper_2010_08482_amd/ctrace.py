@@ -28,6 +28,7 @@ CTR_KERNEL_WAVE = 1
 CTR_KERNEL_BLOCK = 2
 CTR_KERNEL_STREAM = 3
 CTR_KERNEL_GROUPED = 4
+CTR_KERNEL_GROUPED_ROWS = 5
 
 
 class ctr_value(ctypes.Structure):
@@ -100,6 +101,7 @@ def _load():
         "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
         "ctr_strings": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32)]),
         "ctr_synchronize": (ctypes.c_int, [vp]),
+        "ctr_last_kernel": (ctypes.c_int, [vp, P(i32), P(i32)]),
         "ctr_probe_peaks": (ctypes.c_int, [vp, P(f64)]),
         "ctr_kernel_timing": (ctypes.c_int, [vp, i32]),
         "ctr_kernel_timing_read": (ctypes.c_int, [vp, P(f64), P(i32)]),
@@ -303,6 +305,13 @@ def ctr_probe_peaks(ctx):
     _check(ctx, _lib.ctr_probe_peaks(ctx, _ptr(out, ctypes.c_double)))
     return {"fp64_mfma_16x16x4_tflops": float(out[0]), "fp64_mfma_4x4x4_tflops": float(out[1]),
             "fp32_mfma_16x16x4_tflops": float(out[2]), "clock_mhz": float(out[3]), "compute_units": int(out[4])}
+
+
+def ctr_last_kernel(ctx):
+    """(CTR_KERNEL_* the last trace call ran, FP32-split slices or 0)."""
+    k, sl = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, _lib.ctr_last_kernel(ctx, ctypes.byref(k), ctypes.byref(sl)))
+    return int(k.value), int(sl.value)
 
 
 def ctr_synchronize(ctx) -> None:

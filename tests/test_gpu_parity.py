@@ -55,7 +55,7 @@ def ctx(lib):
         c.close()
 
 
-HIST_KERNELS = {"wave": 1, "block": 2, "stream": 3, "grouped": 4}
+HIST_KERNELS = {"wave": 1, "block": 2, "stream": 3, "grouped": 4, "grouped_rows": 5}
 
 
 def pair(v):
@@ -85,6 +85,27 @@ def check_against(out, refs, scales, label):
         worst = max(worst, rel_err(got, ref))
     say(f"{label}: {len(out)} traces, worst rel err {worst:.2e}, failures {bad[:5]}")
     assert not bad
+
+
+def agree(a, b, label, rtol=1e-10, atol_scale=1e-12):
+    """Two GPU evaluations of the same batch against each other at the R14 bar:
+    |a - b| <= rtol |b|, or <= atol_scale exp(log_abs) for cancellation-
+    dominated traces (log_abs: the sum of moduli of the evaluated
+    contributions, never above the oracle's Lehmann modulus sum)."""
+    assert np.array_equal(a["flags"], b["flags"]) and np.array_equal(a["n_strings"], b["n_strings"]), label
+    worst = 0.0
+    cancel = 0
+    for x, y in zip(a, b):
+        if y["re"] == 0 and y["im"] == 0:
+            assert x["re"] == 0 and x["im"] == 0, label
+            continue
+        scale = (1.0, max(float(x["log_abs"]), float(y["log_abs"])))
+        assert close_enough(pair(x), pair(y), scale, rtol, atol_scale), (label, rel_err(pair(x), pair(y)))
+        r = rel_err(pair(x), pair(y))
+        worst = max(worst, r)
+        cancel += r > rtol
+    say(f"{label}: worst rel {worst:.2e}, {cancel} cancellation-dominated")
+    return worst
 
 
 # ---------------------------------------------------------------------------
@@ -218,8 +239,8 @@ def test_complex_impurities_vs_golden(ctx, name):
                   name)
 
 
-@pytest.mark.parametrize("name,kernels", [("fshell_low", ("block", "stream", "grouped")),
-                                          ("fshell_cf_low", ("stream",))])
+@pytest.mark.parametrize("name,kernels", [("fshell_low", ("block", "stream", "grouped", "grouped_rows")),
+                                          ("fshell_cf_low", ("stream", "grouped"))])
 def test_generic_fshell_low_orders_vs_golden(lib, ctx, name, kernels):
     """The generic 16384-state f-shell impurities against the dense oracle at
     the few low orders it affords (stored values), every kernel that runs them."""
@@ -262,13 +283,8 @@ def test_fshell_gauge_invariance(ctx):
     cfgs = make_configs(2, 40)
     say("[gpu] ctr_trace_batch fshell (complex) vs fshell_real x40")
     a, b = cg.trace_batch(cfgs), cr.trace_batch(cfgs)
-    n_nz = 0
-    for i, (x, y) in enumerate(zip(a, b)):
-        if y["re"] == 0:
-            continue
-        n_nz += 1
-        assert rel_err(pair(x), pair(y)) < 1e-9, i
-    assert n_nz >= 10
+    agree(a, b, "fshell complex vs real (gauge)")
+    assert sum(1 for y in b if y["re"] != 0) >= 10
 
 
 # ---------------------------------------------------------------------------
@@ -282,21 +298,26 @@ def test_cyclicity_and_anticommutation_dshell(ctx):
     rng = np.random.Generator(np.random.PCG64(3))
     beta = tab.beta
     say("[gpu] cyclicity / anticommutation dshell")
+    # bar R14 with the cancellation scale of the evaluations themselves (log_abs)
+    def scale(*vs):
+        return 1.0, max(float(v["log_abs"]) for v in vs)
+
     for i in range(20):
         s = random_string(rng, 10, beta, 2 * int(rng.integers(5, 30)), "alternating")
-        w = pair(c.trace(s.tau, s.op))
+        vw = c.trace(s.tau, s.op)
+        w = pair(vw)
         d = float(rng.uniform(0, beta))
         t2 = (s.tau + d) % beta
         o = np.argsort(t2, kind="stable")
-        w2 = pair(c.trace(t2[o], s.op[o]))
+        v2 = c.trace(t2[o], s.op[o])
         if w[0] != 0:
-            assert rel_err(w2, w) < 1e-9, i
+            assert close_enough(pair(v2), w, scale(vw, v2)), (i, rel_err(pair(v2), w))
         t_new = float(rng.uniform(0, beta))
         f = int(rng.integers(10))
-        a = pair(c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f + 1, 2 * f])))
-        b = pair(c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f, 2 * f + 1])))
+        va = c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f + 1, 2 * f]))
+        vb = c.trace(*insert_ops(s.tau, s.op, t_new, [2 * f, 2 * f + 1]))
         if w[0] != 0:
-            assert rel_err(add(a, b), w) < 1e-9, i
+            assert close_enough(add(pair(va), pair(vb)), w, scale(vw, va, vb)), (i, rel_err(add(pair(va), pair(vb)), w))
 
 
 # ---------------------------------------------------------------------------
@@ -396,20 +417,17 @@ def test_grouped_rounds_agree_with_per_string_kernels(lib, ctx):
     tab, c = ctx("dshell")
     cfgs = make_configs(1, 2000)
     say("[gpu] grouped vs wavefront dshell x2000")
-    a = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
     b = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_WAVE)
-    assert np.array_equal(a["flags"], b["flags"]) and np.array_equal(a["n_strings"], b["n_strings"])
-    worst = max((rel_err(pair(x), pair(y)) for x, y in zip(a, b) if y["re"] != 0), default=0.0)
-    say(f"grouped vs wavefront worst rel {worst:.2e}")
-    assert worst < 1e-11
+    for k in (lib.CTR_KERNEL_GROUPED, lib.CTR_KERNEL_GROUPED_ROWS):
+        a = c.trace_batch(cfgs, kernel=k)
+        assert agree(a, b, f"grouped {k} vs wavefront dshell") < 1e-11
     tab, c = ctx("fshell")
     cfgs = make_configs(2, 300)
     say("[gpu] grouped vs block fshell x300")
-    a = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
     b = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_BLOCK)
-    worst = max((rel_err(pair(x), pair(y)) for x, y in zip(a, b) if y["re"] != 0 or y["im"] != 0), default=0.0)
-    say(f"grouped vs block fshell worst rel {worst:.2e}")
-    assert worst < 1e-9
+    for k in (lib.CTR_KERNEL_GROUPED, lib.CTR_KERNEL_GROUPED_ROWS):
+        a = c.trace_batch(cfgs, kernel=k)
+        agree(a, b, f"grouped {k} vs block fshell")
 
 
 def test_determinism_and_batch_order(ctx):
@@ -484,12 +502,11 @@ def test_lazy_refinement_rejects_only_below_threshold(lib, ctx, name, cid, count
     say(f"lazy refinement {name}: {int(np.sum(rej))} of {int(np.sum(thr > la))} rejectable configurations rejected")
 
 
-@pytest.mark.parametrize("kernel", ["wave", "block", "stream", "grouped"])
+@pytest.mark.parametrize("kernel", ["wave", "block", "stream", "grouped", "grouped_rows"])
 def test_every_chain_kernel_matches_the_oracle(lib, ctx, kernel):
     """The chain kernels (wavefront, LDS workgroup, streaming, block-grouped
-    rounds) forced on impurities the oracle covers."""
-    k = {"wave": lib.CTR_KERNEL_WAVE, "block": lib.CTR_KERNEL_BLOCK, "stream": lib.CTR_KERNEL_STREAM,
-         "grouped": lib.CTR_KERNEL_GROUPED}[kernel]
+    rounds, row-chunked grouped rounds) forced on impurities the oracle covers."""
+    k = HIST_KERNELS[kernel]
     g = load_golden("dshell_config1")
     tab, c = ctx("dshell")
     recs = g["records"][:96]
@@ -515,9 +532,6 @@ def test_kernel_option_errors(lib, ctx):
         c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_STREAM)
     assert e.value.status == -7
     with pytest.raises(lib.CtraceError) as e:
-        c.trace([0.5, 1.0], [1, 0], precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED)
-    assert e.value.status == -7
-    with pytest.raises(lib.CtraceError) as e:
         c.trace([0.5, 1.0], [1, 0], kernel=7)
     assert e.value.status == -1
 
@@ -525,24 +539,23 @@ def test_kernel_option_errors(lib, ctx):
 @pytest.mark.parametrize("phase_seed", [None, 11])
 def test_sectors_of_3432_states_density_density_vs_enumeration(lib, ctx, phase_seed):
     """N-only sectors of the 14-flavor shell (largest 3432 states): the
-    streaming kernel, checked against exact state enumeration."""
+    streaming kernel and the (row-chunked) grouped rounds, checked against
+    exact state enumeration."""
     from oracle import densdens_trace
 
     tab, c = ctx("dd_fshell_n", phase_seed)
     assert tab.max_dim == 3432
     imp = make_impurity("dd_fshell_n")
     cfgs = make_configs(3, 10)  # 14 flavors, beta 40, orders 60..200
-    say(f"[gpu] ctr_trace_batch dd_fshell_n phase={phase_seed} x{len(cfgs)}")
-    out = c.trace_batch(cfgs)
     refs = [densdens_trace(imp, s.tau, s.op) for s in cfgs]
     scales = [densdens_trace(imp, s.tau, s.op, moduli=True) for s in cfgs]
-    check_against(out, refs, scales, f"dd_fshell_n phase={phase_seed}")
+    for k in ("stream", "grouped"):
+        say(f"[gpu] ctr_trace_batch dd_fshell_n phase={phase_seed} x{len(cfgs)} kernel={k}")
+        out = c.trace_batch(cfgs, kernel=HIST_KERNELS[k])
+        check_against(out, refs, scales, f"dd_fshell_n phase={phase_seed} {k}")
     assert sum(1 for r in refs if r[0] != 0) >= 5
     with pytest.raises(lib.CtraceError) as e:
         c.trace(cfgs[0].tau, cfgs[0].op, kernel=lib.CTR_KERNEL_BLOCK)
-    assert e.value.status == -7
-    with pytest.raises(lib.CtraceError) as e:
-        c.trace(cfgs[0].tau, cfgs[0].op, kernel=lib.CTR_KERNEL_GROUPED)
     assert e.value.status == -7
 
 
@@ -559,8 +572,8 @@ def test_fp32_split_d_shell_vs_golden_and_fp64(lib, ctx):
     check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
                   "config1 fp32-split vs oracle")
     f64 = c.trace_batch(cfgs)
-    worst = max(rel_err(pair(a), pair(b)) for a, b in zip(out, f64) if b["re"] != 0)
-    say(f"config1 fp32-split vs fp64 worst rel {worst:.2e}")
+    # six slices against the FP64 path at the R14 bar (cancellation scale log_abs)
+    agree(out, f64, "config1 fp32-split (6 slices) vs fp64")
 
 
 def test_fp32_split_seven_slices_d_shell_vs_golden_and_fp64(lib, ctx):
@@ -580,14 +593,57 @@ def test_fp32_split_seven_slices_d_shell_vs_golden_and_fp64(lib, ctx):
 
 
 @pytest.mark.parametrize("name", ["pshell_random", "dshell_so_random"])
-def test_fp32_split_complex_vs_golden(lib, ctx, name):
+@pytest.mark.parametrize("kernel,slices", [("block", 6), ("grouped", 6), ("grouped", 7)])
+def test_fp32_split_complex_vs_golden(lib, ctx, name, kernel, slices):
+    """FP32-split on the per-string LDS kernel and on the row-chunked grouped
+    rounds against stored oracle values."""
     g = load_golden(name)
     tab, c = ctx(g["impurity"])
     strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
-    say(f"[gpu] ctr_trace_batch FP32_SPLIT {name}")
-    out = c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT)
+    say(f"[gpu] ctr_trace_batch FP32_SPLIT {name} kernel={kernel} slices={slices}")
+    out = c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=HIST_KERNELS[kernel], slices=slices)
     check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
-                  name + " fp32-split")
+                  f"{name} fp32-split {kernel} {slices}")
+
+
+@pytest.mark.parametrize("name", ["fshell_low", "fshell_cf_low"])
+def test_fp32_split_generic_fshell_vs_golden(lib, ctx, name):
+    """FP32-split (seven slices, grouped rounds) on the generic 16384-state
+    f-shell impurities, (N, Jz) and crystal-field, against the dense oracle."""
+    g = load_golden(name)
+    tab, c = ctx(g["impurity"])
+    strings = [(np.array(r["tau"]), np.array(r["op"], dtype=np.int32)) for r in g["records"]]
+    say(f"[gpu] ctr_trace_batch FP32_SPLIT {name} x{len(strings)}")
+    out = c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7)
+    check_against(out, [golden_pair(r) for r in g["records"]], [(r["abs"], r["abs_log"]) for r in g["records"]],
+                  f"{name} fp32-split")
+
+
+@pytest.mark.parametrize("name,cid,count", [("dd_fshell", 2, 48), ("dd_fshell_n", 3, 10)])
+def test_fp32_split_fshell_size_density_density_vs_enumeration(lib, ctx, name, cid, count):
+    """FP32-split at full f-shell size and workload orders (40-160, 60-200),
+    phase-randomised complex blocks, against exact state enumeration."""
+    from oracle import densdens_trace
+
+    tab, c = ctx(name, 7)
+    imp = make_impurity(name)
+    cfgs = make_configs(cid, count)
+    say(f"[gpu] FP32_SPLIT {name} x{len(cfgs)}")
+    out = c.trace_batch(cfgs, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7)
+    refs = [densdens_trace(imp, s.tau, s.op) for s in cfgs]
+    scales = [densdens_trace(imp, s.tau, s.op, moduli=True) for s in cfgs]
+    check_against(out, refs, scales, f"{name} fp32-split")
+
+
+def test_fp32_split_fshell_workload_vs_fp64(lib, ctx):
+    """FP32-split (seven slices) against the FP64 path on 300 workload
+    configurations of the generic f-shell (N, Jz) at orders 40-160, R14 bar."""
+    tab, c = ctx("fshell")
+    cfgs = make_configs(2, 300)
+    say("[gpu] FP32_SPLIT vs FP64 fshell x300")
+    a = c.trace_batch(cfgs, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7)
+    b = c.trace_batch(cfgs, kernel=lib.CTR_KERNEL_GROUPED)
+    agree(a, b, "fshell fp32-split (7) vs fp64")
 
 
 def test_fp32_split_rejects_unsupported_slices(lib, ctx):
@@ -726,7 +782,8 @@ def test_maximum_operator_count_vs_oracle(lib, ctx):
         strings = [random_string(rng, imp.n_flavors, imp.beta, n, "alternating") for n in orders]
         refs = [dt.trace(s.tau, s.op) for s in strings]
         scales = [dt.abs_scale(s.tau, s.op) for s in strings]
-        kernels = [lib.CTR_KERNEL_WAVE, lib.CTR_KERNEL_BLOCK, lib.CTR_KERNEL_STREAM, lib.CTR_KERNEL_GROUPED]
+        kernels = [lib.CTR_KERNEL_WAVE, lib.CTR_KERNEL_BLOCK, lib.CTR_KERNEL_STREAM, lib.CTR_KERNEL_GROUPED,
+                   lib.CTR_KERNEL_GROUPED_ROWS]
         for k in kernels:
             say(f"[gpu] maximum orders {name} {orders} kernel={k}")
             out = c.trace_batch(strings, kernel=k)
@@ -753,14 +810,15 @@ def test_grouped_rounds_on_degenerate_batches(lib, ctx):
     for batch in ([z] * 300, [odd, dead] * 150, [z, odd, dead, two] * 75 + list(
             (s.tau, s.op) for s in make_configs(1, 60))):
         say(f"[gpu] grouped degenerate batch of {len(batch)}")
-        g = c.trace_batch(batch, kernel=lib.CTR_KERNEL_GROUPED)
         w = c.trace_batch(batch, kernel=lib.CTR_KERNEL_WAVE)
-        assert np.array_equal(g["flags"], w["flags"]) and np.array_equal(g["n_strings"], w["n_strings"])
-        for a, b in zip(g, w):
-            if b["re"] == 0 and b["im"] == 0:
-                assert a["re"] == 0 and a["im"] == 0
-            else:
-                assert rel_err(pair(a), pair(b)) < 1e-12
+        for k in (lib.CTR_KERNEL_GROUPED, lib.CTR_KERNEL_GROUPED_ROWS):
+            g = c.trace_batch(batch, kernel=k)
+            assert np.array_equal(g["flags"], w["flags"]) and np.array_equal(g["n_strings"], w["n_strings"])
+            for a, b in zip(g, w):
+                if b["re"] == 0 and b["im"] == 0:
+                    assert a["re"] == 0 and a["im"] == 0
+                else:
+                    assert rel_err(pair(a), pair(b)) < 1e-12
     with pytest.raises(lib.CtraceError) as e:
         c.trace_batch([OperatorString(np.array([2.0, 1.0]), np.array([1, 0], dtype=np.int32))],
                       kernel=lib.CTR_KERNEL_GROUPED)
