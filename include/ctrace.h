@@ -26,7 +26,9 @@
  *  - Memory: the library never allocates device memory.  Everything it
  *    keeps (operator blocks, tables, kernel buffers, per-call scratch) is carved out of the
  *    arena the caller passes to ctr_create (pre-allocated device pool, as in
- *    Sec. 3.3.2).  Running out of arena returns CTR_ERR_OOM and leaves the
+ *    Sec. 3.3.2), except the per-call scratch of ctr_trace_batch_device_static,
+ *    which lives in a fixed array of the library's code object on every
+ *    device.  Running out of arena returns CTR_ERR_OOM and leaves the
  *    context usable.
  *  - Threads: a context is not thread safe; use one per host thread.
  *  - Errors: no exceptions cross the ABI; ctr_last_error gives detail.
@@ -223,6 +225,29 @@ ctr_status ctr_trace_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, 
 ctr_status ctr_trace_batch_device(ctr_ctx *ctx, int32_t n_cfg, const int64_t *d_offsets,
                                   const double *d_tau, const int32_t *d_op, const ctr_opts *opts,
                                   ctr_value *d_out);
+
+/*
+ * For callers that cannot allocate device memory per call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same traces as ctr_trace_batch_device, with the per-call scratch (string
+ * records, panel results, per-configuration counters) taken from a fixed
+ * array of CTR_STATIC_SCRATCH_BYTES that the library keeps on every device it
+ * runs on until the process ends, instead of from the context's arena.  The
+ * call allocates nothing (no hipMalloc, no events) and only enqueues work.
+ * It runs the per-string chain kernels (AUTO never takes the grouped rounds
+ * here; asking for CTR_KERNEL_GROUPED or CTR_KERNEL_GROUPED_ROWS gives
+ * CTR_ERR_UNSUPPORTED).  A batch
+ * whose scratch exceeds the array is rejected with CTR_ERR_OOM before any
+ * device work (the message states the bytes it needs); it is not split.
+ * Every call on one device shares that device's array: calls whose work
+ * overlaps on the device (other streams, other contexts or threads) race and
+ * must be serialised by the caller.  Other arguments and errors as
+ * ctr_trace_batch_device.
+ */
+#define CTR_STATIC_SCRATCH_BYTES (64u << 20)
+ctr_status ctr_trace_batch_device_static(ctr_ctx *ctx, int32_t n_cfg, const int64_t *d_offsets,
+                                         const double *d_tau, const int32_t *d_op, const ctr_opts *opts,
+                                         ctr_value *d_out);
 
 /*
  * Lazy traces (Sec. 3.3.1, lazy-trace bounds): per configuration, the

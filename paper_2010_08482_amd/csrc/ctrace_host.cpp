@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,18 @@ struct ctr_ctx {
 };
 
 namespace {
+
+// Per-call scratch of ctr_trace_batch_device_static: a fixed device array
+// instead of the context's arena.  Each device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address hipGetSymbolAddress
+// returned for the current device (g_scratch), taken once per device in
+// ctr_create.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -522,7 +535,17 @@ ctr_status ctr_create(int device, void* arena, size_t arena_bytes, void* hip_str
   *out = nullptr;
   if (arena_bytes < (1u << 20)) return CTR_ERR_ARG;
   if (((uintptr_t)arena) % kAlign) return CTR_ERR_ARG;
+  if (device < 0 || device >= kMaxDevices) return CTR_ERR_ARG;
   if (hipSetDevice(device) != hipSuccess) return CTR_ERR_DEVICE;
+  {
+    // device address of this device's static scratch array, once per device
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CTR_ERR_DEVICE;
+      g_scratch[device] = p;
+    }
+  }
   ctr_ctx* ctx = new ctr_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
@@ -978,6 +1001,45 @@ ctr_status ctr_trace_batch_device(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_
     c0 += m;
   }
   return CTR_OK;
+}
+
+ctr_status ctr_trace_batch_device_static(ctr_ctx* ctx, int32_t n_cfg, const int64_t* d_offsets, const double* d_tau,
+                                         const int32_t* d_op, const ctr_opts* opts, ctr_value* d_out) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  bool split = false;
+  Kernel kind = Kernel::Block;
+  if ((s = check_opts(ctx, opts, &split, &kind, n_cfg)) != CTR_OK) return s;
+  if (kind == Kernel::Group) {
+    // the grouped rounds size their scratch from a device count read back mid-call
+    if (opts && (opts->kernel == CTR_KERNEL_GROUPED || opts->kernel == CTR_KERNEL_GROUPED_ROWS))
+      return fail(ctx, CTR_ERR_UNSUPPORTED, "the static-scratch entry point runs the per-string kernels only");
+    kind = per_string_kernel(ctx);
+  }
+  if (n_cfg < 0 || (n_cfg > 0 && (!d_offsets || !d_out))) return fail(ctx, CTR_ERR_ARG, "null argument");
+  if (n_cfg == 0) return CTR_OK;
+  void* base = g_scratch[ctx->device];
+  if (!base) return fail(ctx, CTR_ERR_STATE, "static scratch address not set up for this device");
+  Bump b{(char*)base, 0, kStaticScratchBytes};
+  BatchArgs a{};
+  if (!carve(ctx, b, n_cfg, a)) {
+    Bump probe{(char*)kAlign, 0, SIZE_MAX / 2};  // sizes only, never dereferenced
+    BatchArgs t{};
+    carve(ctx, probe, n_cfg, t);
+    return fail(ctx, CTR_ERR_OOM, "batch needs " + std::to_string(probe.off >> 10) + " KiB of per-call scratch; the "
+                                      "static array holds " + std::to_string(kStaticScratchBytes >> 10) + " KiB");
+  }
+  a.offsets = (const long long*)d_offsets;
+  a.tau = d_tau;
+  a.op = d_op;
+  a.log_thr = nullptr;
+  a.out = d_out;
+  // no events either: this call creates nothing
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  s = enqueue(ctx, a, false, split, kind, nullptr);
+  ctx->timing = timing;
+  return s;
 }
 
 ctr_status ctr_probe_peaks(ctr_ctx* ctx, double* out) {

@@ -74,6 +74,7 @@ RESULT_DTYPE = np.dtype([("tag", "<u8"), ("impurity", "<i4"), ("status", "<i4"),
                          ("latency_ms", "<f8"), ("batch", "<i4"), ("reserved", "<i4")])
 assert RESULT_DTYPE.itemsize == ctypes.sizeof(ctr_result)
 CTR_ERR_BUSY = -8
+CTR_STATIC_SCRATCH_BYTES = 64 << 20  # ctr_trace_batch_device_static: per-call scratch array per device
 
 
 def _load():
@@ -94,6 +95,7 @@ def _load():
         "ctr_trace": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(ctr_opts), P(ctr_value)]),
         "ctr_trace_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(ctr_opts), P(ctr_value)]),
         "ctr_trace_batch_device": (ctypes.c_int, [vp, i32, vp, vp, vp, P(ctr_opts), vp]),
+        "ctr_trace_batch_device_static": (ctypes.c_int, [vp, i32, vp, vp, vp, P(ctr_opts), vp]),
         "ctr_trace_lazy_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(f64), P(ctr_opts),
                                                 P(ctr_value)]),
         "ctr_trace_histogram": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), i32, P(ctr_opts),
@@ -250,6 +252,15 @@ def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out
     _check(ctx, _lib.ctr_trace_batch_device(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
                                             ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
                                             ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
+
+
+def ctr_trace_batch_device_static(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64,
+                                  kernel=CTR_KERNEL_AUTO, slices=0):
+    """As ctr_trace_batch_device, per-call scratch in the library's fixed device array."""
+    o = _opts(precision, kernel, slices)
+    _check(ctx, _lib.ctr_trace_batch_device_static(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
+                                                   ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
+                                                   ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
 
 
 def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
