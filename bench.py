@@ -301,12 +301,15 @@ def cpu_block_sparse(tab, strings, seconds_budget=5.0):
 
 def serve_main(args, emit: bool = True):
     """Serving mix: 256 Markov chains spread over the d-shell, f-shell (N, Jz)
-    and, with --serve-cf, crystal-field f-shell impurities; trace requests arrive
-    as a Poisson stream, each the chain's configuration after one pair
-    insertion or removal (App. D moves), orders starting from N(100, 30)
-    clipped to [2, 240].  Open loop: requests are submitted at their arrival
-    times whatever the server's state; reports the achieved throughput and the
-    latency percentiles per impurity.  Prints one JSON line."""
+    and crystal-field f-shell impurities (62.5 / 25 / 12.5%; without the
+    crystal field 75 / 25%); trace requests arrive as a Poisson stream, each
+    the chain's configuration after one pair insertion or removal (App. D
+    moves), orders starting from N(100, 30) clipped to [2, 240].  A chain has
+    at most one request in flight (its next move depends on the decision): an
+    arrival that picks a chain whose proposal is still on the GPU makes no
+    move (counted).  Admission per impurity by arena footprint (hbm_budget), a
+    stream and a grid share per impurity.  Reports throughput and latency
+    percentiles per impurity from submission to result.  Prints one JSON line."""
     import threading
 
     import torch
@@ -320,12 +323,13 @@ def serve_main(args, emit: bool = True):
     chain_share = [0.75, 0.25] if not args.serve_cf else [0.625, 0.25, 0.125]
     imps = [make_impurity(n) for n in names]
     free, _ = torch.cuda.mem_get_info(0)
+    budget = int(args.serve_budget_gib * (1 << 30))
     ctxs = []
     for imp in imps:
         tab = build_sectors(imp)
         print(f"[serve] {imp.name}: {tab.n_sectors} sectors, largest block {tab.max_dim}", file=sys.stderr, flush=True)
         # a stream per impurity, so that the lanes' passes overlap on the device
-        ctxs.append(ctrace.TraceContext(tab, scratch_bytes=int(min(free // (4 * len(imps)), 16 << 30)),
+        ctxs.append(ctrace.TraceContext(tab, scratch_bytes=int(min(free // (4 * len(imps)), max(budget, 1 << 30) + (1 << 30))),
                                         stream=torch.cuda.Stream()))
     rng = np.random.Generator(np.random.PCG64(2024))
     n_chains = 256
@@ -335,40 +339,59 @@ def serve_main(args, emit: bool = True):
         imp = imps[kind[c]]
         n = int(np.clip(round(rng.normal(100.0, 30.0) / 2) * 2, 2, 240))
         chains.append(random_string(rng, imp.n_flavors, imp.beta, n, "alternating"))
-    n_req = int(args.serve_rate * args.serve_seconds)
-    t_arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n_req))
-    reqs = []
-    for i in range(n_req):
-        c = int(rng.integers(n_chains))
-        imp = imps[kind[c]]
-        s = chains[c]
-        if s.n <= 2 or (s.n + 2 <= 240 and rng.uniform() < 0.5):
-            s = insert_pair(rng, s, imp.n_flavors, imp.beta)
-        else:
-            s = remove_pair(rng, s, imp.n_flavors)
-        chains[c] = s
-        reqs.append((int(kind[c]), s))
+    n_arr = int(args.serve_rate * args.serve_seconds)
+    t_arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n_arr))
+    c_arr = rng.integers(n_chains, size=n_arr)
+    mrng = np.random.Generator(np.random.PCG64(2025))  # moves, in issue order
+    reqs = []   # (chain, impurity, string), in issue order
     share = [float(x) for x in args.serve_grid_share.split(",")] if args.serve_grid_share else None
-    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch, grid_share=share)
+    if share is not None:
+        share = (share + [1.0] * len(names))[: len(names)]
+    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch, hbm_budget=budget, grid_share=share)
     results = []
+    lock = threading.Lock()
+    busy_chain = np.zeros(n_chains, dtype=bool)
+    dropped = 0
     done = threading.Event()
 
     def collect():
-        while not done.is_set() or len(results) < n_req:
+        while True:
             r = srv.poll(max_results=8192, wait=True)
-            results.extend(r.tolist())
-            if done.is_set() and len(r) == 0:
-                break
+            if len(r) == 0:
+                if done.is_set():
+                    break
+                time.sleep(2e-4)  # nothing in flight
+                continue
+            rows = r.tolist()
+            with lock:
+                results.extend(rows)
+                for row in rows:
+                    busy_chain[reqs[int(row[0])][0]] = False
 
     poller = threading.Thread(target=collect)
     poller.start()
-    busy = 0
     t0 = time.perf_counter()
-    for i, (k, s) in enumerate(reqs):
-        while time.perf_counter() - t0 < t_arr[i]:
+    for a in range(n_arr):
+        while time.perf_counter() - t0 < t_arr[a]:
             pass
-        while srv.submit(k, i, s.tau, s.op) == ctrace.CTR_ERR_BUSY:
-            busy += 1
+        c = int(c_arr[a])
+        with lock:
+            if busy_chain[c]:
+                # the chain's previous proposal is still being decided: no new move from it
+                dropped += 1
+                continue
+            busy_chain[c] = True
+        imp = imps[kind[c]]
+        s = chains[c]
+        if s.n <= 2 or (s.n + 2 <= 240 and mrng.uniform() < 0.5):
+            s = insert_pair(mrng, s, imp.n_flavors, imp.beta)
+        else:
+            s = remove_pair(mrng, s, imp.n_flavors)
+        chains[c] = s
+        i = len(reqs)
+        reqs.append((c, int(kind[c]), s))
+        while srv.submit(int(kind[c]), i, s.tau, s.op) == ctrace.CTR_ERR_BUSY:
+            pass
     t_sub = time.perf_counter() - t0
     srv.drain()
     t_end = time.perf_counter() - t0
@@ -377,6 +400,7 @@ def serve_main(args, emit: bool = True):
     results.extend(srv.poll(max_results=8192).tolist())
     passes, evaluated = srv.stats()
     srv.close()
+    n_req = len(reqs)
     lat = np.array([r[4] for r in results])
     imp_of = np.array([r[1] for r in results])
     bat = np.array([r[5] for r in results])
@@ -385,7 +409,8 @@ def serve_main(args, emit: bool = True):
         m = imp_of == k
         if m.any():
             per[n] = {"requests": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
-                      "p99_ms": float(np.percentile(lat[m], 99)), "mean_batch": float(bat[m].mean())}
+                      "p99_ms": float(np.percentile(lat[m], 99)), "mean_batch": float(bat[m].mean()),
+                      "chains": int(np.sum(kind == k))}
     line = {
         "metric": "serving: trace requests/s with p50/p99 latency (continuous batching)",
         "value": len(results) / t_end,
@@ -393,20 +418,23 @@ def serve_main(args, emit: bool = True):
         "n_gpus": 1,
         "higher_is_better": True,
         "offered_rate": args.serve_rate,
+        "arrivals": n_arr,
+        "arrivals_on_busy_chains": dropped,
         "submit_seconds": t_sub,
         "seconds": t_end,
         "requests": n_req,
         "completed": len(results),
         "statuses_ok": int(sum(1 for r in results if r[2] == 0)),
-        "busy_retries": busy,
         "device_passes": passes,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "from": "ctr_server_submit to result"},
         "per_impurity": per,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "serving mix: 256 chains, Poisson arrivals, pair insert/remove moves",
+        "config": {"workload": "serving mix: 256 Markov chains, Poisson arrivals, pair insert/remove moves, "
+                               "one request in flight per chain",
                    "impurities": names, "chain_share": chain_share, "max_batch": args.serve_batch,
-                   "grid_share": share, "streams": "one per impurity"},
+                   "hbm_budget_bytes": budget, "grid_share": share, "streams": "one per impurity"},
     }
     for c in ctxs:
         c.close()
@@ -481,7 +509,8 @@ def throughput_leg(wl_id, n_configs, batch, steps, warmup, kernel_opt, split_con
 
     for k in range(warmup):
         run(k)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup step {k + 1}/{warmup} done", file=sys.stderr, flush=True)
     ctrace.ctr_kernel_timing(ctx.ctx, True)
     ctrace.ctr_kernel_timing_read(ctx.ctx)
     torch.cuda.synchronize()
@@ -489,6 +518,8 @@ def throughput_leg(wl_id, n_configs, batch, steps, warmup, kernel_opt, split_con
     t0 = time.perf_counter()
     for k in range(steps):
         done += run(k)
+        # progress (host side: the grouped rounds wait once per batch for their schedule)
+        print(f"[bench] step {k + 1}/{steps} enqueued ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     chain_ms, launches = ctrace.ctr_kernel_timing_read(ctx.ctx)
@@ -520,6 +551,7 @@ def throughput_leg(wl_id, n_configs, batch, steps, warmup, kernel_opt, split_con
     if split_configs:
         # FP32-split leg: block products on FP32 MFMA over exact 8-bit slices, first configurations
         m = min(split_configs, n_cfg)
+        print(f"[bench] FP32-split leg: {m} configurations", file=sys.stderr, flush=True)
         d_s = torch.zeros_like(d_out)
         d_f = torch.zeros_like(d_out)
         run(0, ctrace.CTR_FP64, d_f, m)
@@ -551,10 +583,12 @@ def throughput_leg(wl_id, n_configs, batch, steps, warmup, kernel_opt, split_con
 
     if lazy_sample:
         lz = strings[:lazy_sample]
+        print(f"[bench] lazy leg: {len(lz)} proposals", file=sys.stderr, flush=True)
         full = ctx.trace_batch(lz)
         rec["lazy"] = lazy_leg(ctx, imp, lz, full)
 
     if not no_cpu:
+        print("[bench] CPU baselines", file=sys.stderr, flush=True)
         if wl_id == 1:
             sample = strings[:24]
             rate, got, el, threads, refs = cpu_baseline(imp, sample)
@@ -590,6 +624,7 @@ def dshell_extras(args):
     tab = build_sectors(imp)
     strings = make_configs(1)
     ctx = ctrace.TraceContext(tab, scratch_bytes=8 << 30)
+    print("[bench] d-shell histogram, Markov and latency legs", file=sys.stderr, flush=True)
     rec = {"histogram": histogram_leg(ctx, tab, imp, strings)}
     if args.mc_chains > 0:
         mk = markov_leg(ctx, "dshell", strings, args.mc_chains, args.mc_steps)
@@ -632,12 +667,15 @@ def main():
                     help="chain kernel of the timed FP64 steps (default: the library's automatic choice)")
     ap.add_argument("--no-also", action="store_true", help="skip the side legs (d-shell, f-shell (N, Jz), serving)")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the throughput step")
-    ap.add_argument("--serve-cf", action="store_true", help="serving mix: add the crystal-field f-shell")
+    ap.add_argument("--serve-no-cf", dest="serve_cf", action="store_false",
+                    help="serving mix: leave out the crystal-field f-shell")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0,
+                    help="serving mix: arena bytes (GiB) one impurity's device pass may occupy")
     ap.add_argument("--serve-rate", type=float, default=5e4, help="serving mix: Poisson arrival rate (1/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="serving mix: seconds of arrivals")
     ap.add_argument("--serve-batch", type=int, default=4096, help="serving mix: most requests per device pass")
-    ap.add_argument("--serve-grid-share", default="",
-                    help="serving mix: per-impurity fractions of the persistent grids, e.g. 1,0.5 (default: full grids)")
+    ap.add_argument("--serve-grid-share", default="1,1,0.5",
+                    help="serving mix: per-impurity fractions of the persistent grids ('' = full grids)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run here has a single MI355X and the trace path has no "
@@ -712,8 +750,8 @@ def main():
             also["dshell extras"] = {"error": f"{type(e).__name__}: {e}"}
         line["also"] = also
         # the serving mix (bench.py --serve for other settings)
-        sargs = argparse.Namespace(**{**vars(args), "serve_rate": 8000.0, "serve_seconds": 2.0,
-                                      "serve_grid_share": "", "serve_cf": False})
+        sargs = argparse.Namespace(**vars(args))
+        print("[bench] serving mix", file=sys.stderr, flush=True)
         try:
             sv = serve_main(sargs, emit=False)
             line["serving"] = {k: sv[k] for k in ("value", "unit", "offered_rate", "completed", "statuses_ok",

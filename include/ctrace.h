@@ -290,6 +290,30 @@ ctr_status ctr_trace_histogram(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offse
                                const ctr_opts *opts, ctr_value *out, double *hist);
 
 /*
+ * The impurity density-matrix estimator (Sec. 2.3.2), tau-integrated, summed
+ * over a batch with caller weights.  For configuration C with trace w(C) != 0
+ *
+ *   R(C) = (beta w(C))^-1 int_0^beta A(tau) dtau,
+ *
+ * where A(tau) is the time-ordered product cut at tau and closed the other
+ * way round (the product that starts and ends at tau, Tr A(tau) = w(C)); it is
+ * block diagonal in the sectors and Tr R(C) = 1.  The tau integral over every
+ * interval between operators is done in closed form in the eigenbasis.
+ *
+ *  weight   host [n_cfg][2] complex weights (re, im) or NULL for 1 each
+ *  out      host [n_cfg] traces of the configurations (as ctr_trace_batch)
+ *  rho      host [sum_q dim_q^2][2]: sum_C weight_C R(C), sector after sector,
+ *           each block row-major [u][v] over the sector's eigenbasis (the order
+ *           of its energies), complex interleaved; overwritten.  Configurations
+ *           whose trace is zero contribute nothing.
+ * Host arrays as ctr_trace_batch; the batch is not split (CTR_ERR_OOM when it
+ * does not fit the arena).  FP64.  Errors: CTR_ERR_UNSUPPORTED for sectors of
+ * more than 1024 states, and those of ctr_trace_batch.
+ */
+ctr_status ctr_density_matrix(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offsets, const double *tau,
+                              const int32_t *op, const double *weight, ctr_value *out, double *rho);
+
+/*
  * Markov chains around the trace (Sec. 2.3.1 sampling; App. C
  * Metropolis-Hastings; App. D Pauli-aware pair insertion and removal;
  * Sec. 2.2 w_hyb).  Each chain holds a configuration, its |w_loc| and the
@@ -442,7 +466,10 @@ typedef struct {
   int32_t max_batch;    /* most requests per device pass and impurity (>= 1) */
   int32_t max_pending;  /* most queued, not yet admitted requests per impurity (>= 1);
                            ctr_server_submit returns CTR_ERR_BUSY beyond it */
-  size_t hbm_budget;    /* per-call scratch bytes a batch may occupy in its context's arena;
+  size_t hbm_budget;    /* arena bytes a batch may occupy in its context's arena (per-call scratch and,
+                           where the grouped rounds can run, the carried matrices of every surviving
+                           sector string of the admitted configurations, estimated by walking the
+                           sector map on the host); at least one request is always admitted;
                            0 = all of the arena not held by the impurity */
   const double *grid_share; /* optional [n_ctx] fractions in (0, 1]: each context launches only that
                            share of the workgroups of its persistent kernels while the server holds

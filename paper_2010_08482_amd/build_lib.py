@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
     objs = []
     for src, extra in (("ctrace_kernels.hip", ["-x", "hip"]), ("ctrace_group.hip", ["-x", "hip"]),
-                       ("ctrace_hist.hip", ["-x", "hip"]),
+                       ("ctrace_hist.hip", ["-x", "hip"]), ("ctrace_rdm.hip", ["-x", "hip"]),
                        ("ctrace_probe.hip", ["-x", "hip"]),
                        ("ctrace_host.cpp", ["-x", "hip"]), ("ctrace_server.cpp", ["-x", "hip"]),
                        ("ctrace_mc.cpp", ["-x", "hip"])):

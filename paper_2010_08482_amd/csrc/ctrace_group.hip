@@ -689,13 +689,13 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
 // exponent it consumed to the column's accumulated one and clears the slot
 // of the round after next.  Closing strings take the diagonal of F * X from
 // the unscaled columns.
-template <bool CPLX, int WR, int WC, int RT, int CT>
+template <bool CPLX, int WR, int WC, int RT, int CT, int KC = 32>
 __global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, GroupArgs G, int r) {
   constexpr int NW = WR * WC;
   constexpr int NT = NW * 64;
   constexpr int RB = WR * RT * 16;
   constexpr int CW = WC * CT * 16;
-  constexpr int KC = 32;                 // rows of X staged in LDS per chunk
+  // KC: rows of X staged in LDS per chunk
   constexpr int LDB = KC + 1;            // odd stride: the 16 columns of a B fragment hit distinct banks
   constexpr int PL = CPLX ? 2 : 1;
   __shared__ double sB[PL * CW * LDB];
@@ -824,17 +824,41 @@ __global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, Gr
           if (CPLX) ri[d][i] = Fi[a];
         }
       }
+    // the next chunk of X is fetched into registers while the current one is multiplied
+    constexpr int NPF = (CW * KC + NT - 1) / NT;
+    double pf_r[NPF], pf_i[NPF];
+    auto fetch = [&](int k0, int kc) {
+#pragma unroll
+      for (int u = 0; u < NPF; ++u) {
+        const int idx = tid + u * NT;
+        pf_r[u] = pf_i[u] = 0.0;
+        if (idx < CW * kc) {
+          const int j = idx / kc, kk = idx - j * kc;
+          const long long g = s_gcol[j];
+          if (g >= 0) {
+            const long long a = g * XR + k0 + kk;
+            pf_r[u] = Xin[a] * s_sc[j];
+            if (CPLX) pf_i[u] = Xin[plane + a] * s_sc[j];
+          }
+        }
+      }
+    };
+    __syncthreads();  // column table visible
+    fetch(0, min(KC, kp));
     for (int k0 = 0; k0 < kp; k0 += KC) {
       const int kc = min(KC, kp - k0);
-      __syncthreads();  // previous chunk consumed; column table visible
-      for (int idx = tid; idx < CW * kc; idx += NT) {
-        const int j = idx / kc, kk = idx - j * kc;
-        const long long g = s_gcol[j];
-        const long long a = g * XR + k0 + kk;
-        sB[j * LDB + kk] = g >= 0 ? Xin[a] * s_sc[j] : 0.0;
-        if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] * s_sc[j] : 0.0;
+      if (k0 > 0) __syncthreads();  // previous chunk consumed
+#pragma unroll
+      for (int u = 0; u < NPF; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < CW * kc) {
+          const int j = idx / kc, kk = idx - j * kc;
+          sB[j * LDB + kk] = pf_r[u];
+          if (CPLX) sB[CW * LDB + j * LDB + kk] = pf_i[u];
+        }
       }
       __syncthreads();
+      if (k0 + KC < kp) fetch(k0 + KC, min(KC, kp - k0 - KC));
       for (int kb = 0; kb < kc; kb += 4 * kPD) {
 #pragma unroll
         for (int d = 0; d < kPD; ++d) {
@@ -1554,9 +1578,10 @@ GVariant make_wvariant() {
   return GVariant{reinterpret_cast<const void*>(&k_gstep_wave<CPLX, MT, CT>), 4, 16 * CT, 0};
 }
 
-template <bool CPLX, int WR, int WC, int RT, int CT>
+template <bool CPLX, int WR, int WC, int RT, int CT, int KC = 32>
 GVariant make_bvariant() {
-  return GVariant{reinterpret_cast<const void*>(&k_gbig<CPLX, WR, WC, RT, CT>), WR * WC, WC * CT * 16, WR * RT * 16};
+  return GVariant{reinterpret_cast<const void*>(&k_gbig<CPLX, WR, WC, RT, CT, KC>), WR * WC, WC * CT * 16,
+                  WR * RT * 16};
 }
 
 template <bool CPLX, int NSL>

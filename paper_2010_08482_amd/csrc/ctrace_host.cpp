@@ -45,6 +45,7 @@ struct ctr_ctx {
   int grid_rsplit[2] = {0, 0};  // their FP32-split form, 6 and 7 slices
   int cw_rsplit = 0, rc_rsplit = 0;
   int last_kernel = 0, last_slices = 0;  // chain kernel and precision of the last trace call
+  std::vector<int> h_dim, h_next;        // host copies of the sector table (footprint estimates)
   bool rows = false;   // the current grouped call runs the row-chunked items
   int gsplit = 0;      // slices of the current grouped call's FP32-split products (0: FP64)
   int galt = 0;        // grouped tile shape: 0 default, 1 the alternative (picked by ctr_tune)
@@ -502,9 +503,24 @@ double context_beta(const ctr_ctx* ctx) { return ctx->beta; }
 int context_nops(const ctr_ctx* ctx) { return ctx->nops; }
 size_t context_free_scratch(const ctr_ctx* ctx) { return ctx->arena_bytes - ctx->resident; }
 void context_set_grid_share(ctr_ctx* ctx, double share) { ctx->grid_share = share; }
-size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops) {
-  return scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
-         (size_t)n_ops * (sizeof(double) + sizeof(int32_t));
+size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops, const int32_t* op) {
+  size_t bytes = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
+                 (size_t)n_ops * (sizeof(double) + sizeof(int32_t));
+  if (ctx->grid_group <= 0 || !op) return bytes;
+  // grouped rounds: every surviving string's columns (its narrowest sector) stay resident as two
+  // copies of the carried matrix, plus per-column and per-column-step schedule entries
+  long long cols = 0;
+  for (int q0 = 0; q0 < ctx->n_sec; ++q0) {
+    int q = q0, w = ctx->h_dim[q0];
+    for (long long i = 0; i < n_ops && q >= 0; ++i) {
+      q = ctx->h_next[(size_t)q * ctx->nops + op[i]];
+      if (q >= 0) w = std::min(w, ctx->h_dim[q]);
+    }
+    if (q == q0) cols += w;
+  }
+  const size_t planes = ctx->imp.is_complex ? 2 : 1;
+  return bytes + (size_t)cols * (2 * (size_t)ctx->imp.xrows * planes * sizeof(double) + 64) +
+         (size_t)cols * (size_t)std::max(n_ops, 1LL) * (sizeof(int) + sizeof(double));
 }
 
 }  // namespace ctr
@@ -757,6 +773,8 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->imp.pool = d_pool;
   ctx->imp.roff = d_roff;
   ctx->imp.rexp = d_rexp;
+  ctx->h_dim = dim;
+  ctx->h_next = next;
   ctx->n_sec = ns;
   ctx->nf = nf;
   ctx->nops = nops;
@@ -924,6 +942,86 @@ ctr_status ctr_trace_histogram(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offse
   const HistReq hr{sector_label, n_labels, hist};
   const bool auto_kind = !opts || opts->kernel == CTR_KERNEL_AUTO;
   return host_batch(ctx, n_cfg, offsets, tau, op, nullptr, out, nullptr, 0, split, kind, nullptr, auto_kind, &hr);
+}
+
+ctr_status ctr_density_matrix(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau,
+                              const int32_t* op, const double* weight, ctr_value* out, double* rho) {
+  ctr_status s = ready(ctx);
+  if (s != CTR_OK) return s;
+  if (n_cfg < 1 || !offsets || !out || !rho) return fail(ctx, CTR_ERR_ARG, "null argument or empty batch");
+  if (ctx->max_dim > ctr::kRdmMaxRows)
+    return fail(ctx, CTR_ERR_UNSUPPORTED, "the density-matrix estimator handles sectors of at most " +
+                                              std::to_string(ctr::kRdmMaxRows) + " states");
+  // the traces first: every contribution is normalised by its configuration's weight
+  if ((s = ctr_trace_batch(ctx, n_cfg, offsets, tau, op, nullptr, out)) != CTR_OK) return s;
+  std::vector<long long> roff(ctx->n_sec);
+  long long entries = 0;
+  for (int q = 0; q < ctx->n_sec; ++q) {
+    roff[q] = entries;
+    entries += (long long)ctx->h_dim[q] * ctx->h_dim[q];
+  }
+  int slots = 1;
+  for (int32_t c = 0; c < n_cfg; ++c) slots = std::max<long long>(slots, offsets[c + 1] - offsets[c]);
+  const long long nops = offsets[n_cfg];
+  Bump b{ctx->arena, ctx->resident, ctx->arena_bytes};
+  long long* d_offs = (long long*)b.take((size_t)(n_cfg + 1) * sizeof(long long));
+  double* d_tau = (double*)b.take((size_t)std::max(nops, 1LL) * sizeof(double));
+  int* d_op = (int*)b.take((size_t)std::max(nops, 1LL) * sizeof(int));
+  double* d_w = (double*)b.take((size_t)n_cfg * 2 * sizeof(double));
+  double* d_wlog = (double*)b.take((size_t)n_cfg * sizeof(double));
+  double* d_weight = (double*)b.take((size_t)n_cfg * 2 * sizeof(double));
+  double* d_rho = (double*)b.take((size_t)entries * 2 * sizeof(double));
+  long long* d_roff = (long long*)b.take((size_t)ctx->n_sec * sizeof(long long));
+  BatchArgs a{};
+  if (!d_offs || !d_tau || !d_op || !d_w || !d_wlog || !d_weight || !d_rho || !d_roff || !carve(ctx, b, n_cfg, a))
+    return fail(ctx, CTR_ERR_OOM, "arena too small for the density-matrix batch");
+  const size_t per_wg = ctr::rdm_buffer_doubles(ctx->imp, slots);
+  const size_t left = b.cap - align_up(b.off);
+  const int grid = (int)std::min<size_t>((size_t)ctr::rdm_grid(ctx->device), left / (per_wg * sizeof(double) + kAlign));
+  double* d_buf = grid > 0 ? (double*)b.take((size_t)grid * per_wg * sizeof(double)) : nullptr;
+  if (!d_buf) return fail(ctx, CTR_ERR_OOM, "arena too small for the density-matrix buffers");
+  std::vector<double> w(2 * (size_t)n_cfg), wlog(n_cfg), wt(2 * (size_t)n_cfg);
+  for (int32_t c = 0; c < n_cfg; ++c) {
+    const bool skip = out[c].flags & (CTR_FLAG_ZERO | CTR_FLAG_REJECTED | CTR_FLAG_INVALID);
+    w[2 * c] = skip ? 0.0 : out[c].re;
+    w[2 * c + 1] = skip ? 0.0 : out[c].im;
+    wlog[c] = out[c].log_scale + ctx->beta * ctx->imp.E0;
+    wt[2 * c] = weight ? weight[2 * c] : 1.0;
+    wt[2 * c + 1] = weight ? weight[2 * c + 1] : 0.0;
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(d_offs, offsets, (size_t)(n_cfg + 1) * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+  if (nops > 0) {
+    HIP_TRY(ctx, hipMemcpyAsync(d_tau, tau, (size_t)nops * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_op, op, (size_t)nops * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_wlog, wlog.data(), wlog.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_weight, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_roff, roff.data(), roff.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(d_rho, 0, (size_t)entries * 2 * sizeof(double), ctx->stream));
+  a.offsets = d_offs;
+  a.tau = d_tau;
+  a.op = d_op;
+  a.log_thr = nullptr;
+  a.out = nullptr;
+  a.panel = ctr::kPanel;
+  hipError_t e = ctr::launch_plan(ctx->imp, a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "plan kernel");
+  if ((e = ctr::launch_scan(a, ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "scan kernel");
+  ctr::RdmArgs r{};
+  r.buf = d_buf;
+  r.per_wg = per_wg;
+  r.slots = slots;
+  r.w = d_w;
+  r.wlog = d_wlog;
+  r.weight = d_weight;
+  r.rho = d_rho;
+  r.rho_off = d_roff;
+  if ((e = ctr::launch_rdm(ctx->imp, a, r, grid, ctx->stream)) != hipSuccess)
+    return hip_fail(ctx, e, "density-matrix kernel");
+  HIP_TRY(ctx, hipMemcpyAsync(rho, d_rho, (size_t)entries * 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CTR_OK;
 }
 
 ctr_status ctr_bound(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double* log_bound) {

@@ -150,7 +150,20 @@ struct HistArgs {
   double* hist;              // [n_cfg][n_labels] complex (re, im)
 };
 
-// Launchers (ctrace_kernels.hip, ctrace_group.hip, ctrace_hist.hip).  All enqueue on `stream`.
+// Density-matrix estimator of a batch (ctrace_rdm.hip), after the traces are known.
+constexpr int kRdmMaxRows = 1024;  // largest sector the estimator handles
+struct RdmArgs {
+  double* buf;                 // per-workgroup buffers, per_wg doubles each
+  size_t per_wg;
+  int slots;                   // stored forward products per string: the batch's largest operator count (>= 1)
+  const double* w;             // [n_cfg][2] trace mantissas (the combine kernel's output)
+  const double* wlog;          // [n_cfg] their log scale + beta E0 (the units of the string shifts L)
+  const double* weight;        // [n_cfg][2] caller weights
+  double* rho;                 // [sum_q dim_q^2][2] output, accumulated with atomic adds
+  const long long* rho_off;    // [n_sec] first entry of every sector's block
+};
+
+// Launchers (ctrace_kernels.hip, ctrace_group.hip, ctrace_hist.hip, ctrace_rdm.hip).  All enqueue on `stream`.
 hipError_t launch_plan(const DevImp& imp, const BatchArgs& b, hipStream_t stream);
 hipError_t launch_scan(const BatchArgs& b, hipStream_t stream);
 // split: 0 = FP64 block products, 6 or 7 = FP32-split with that many 8-bit slices
@@ -180,6 +193,9 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
                               int split, hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+size_t rdm_buffer_doubles(const DevImp& imp, int slots);
+int rdm_grid(int device);
+hipError_t launch_rdm(const DevImp& imp, const BatchArgs& b, const RdmArgs& d, int grid, hipStream_t stream);
 // Peak-rate probe (ctrace_probe.hip): out[0..4] = FP64 16x16x4 and 4x4x4 MFMA and FP32 16x16x4
 // MFMA TFLOP/s, clock (MHz), compute units.  sink: 256 doubles of device memory.
 hipError_t probe_peaks(int device, hipStream_t stream, double* sink, double* out);
@@ -188,7 +204,9 @@ bool context_loaded(const ctr_ctx* ctx);
 double context_beta(const ctr_ctx* ctx);
 int context_nops(const ctr_ctx* ctx);
 size_t context_free_scratch(const ctr_ctx* ctx);          // arena bytes not held by the impurity
-size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops);  // per-call scratch of one configuration
+// Arena bytes one configuration occupies in a batch call: per-call scratch, and with the grouped
+// rounds the carried matrices of its surviving strings (host walk of the sector map).
+size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops, const int32_t* op);
 // Fraction in (0, 1] of every persistent grid the context launches (1 = the whole device).
 void context_set_grid_share(ctr_ctx* ctx, double share);
 

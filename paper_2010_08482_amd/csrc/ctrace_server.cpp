@@ -77,7 +77,8 @@ void run_lane(ctr_server* srv, Lane* L) {
       if (srv->stop.load()) return;
       size_t bytes = 0;
       while (!L->pending.empty() && (int)batch.size() < srv->max_batch) {
-        const size_t need = ctr::request_scratch_bytes(L->ctx, (long long)L->pending.front().op.size());
+        const Request& f = L->pending.front();
+        const size_t need = ctr::request_scratch_bytes(L->ctx, (long long)f.op.size(), f.op.data());
         if (!batch.empty() && bytes + need > L->budget) break;  // admission by scratch footprint
         bytes += need;
         batch.push_back(std::move(L->pending.front()));

@@ -101,6 +101,7 @@ def _load():
         "ctr_trace_histogram": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), i32, P(ctr_opts),
                                                P(ctr_value), P(f64)]),
         "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
+        "ctr_density_matrix": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(f64), P(ctr_value), P(f64)]),
         "ctr_strings": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32)]),
         "ctr_synchronize": (ctypes.c_int, [vp]),
         "ctr_last_kernel": (ctypes.c_int, [vp, P(i32), P(i32)]),
@@ -291,6 +292,30 @@ def ctr_trace_histogram(ctx, offsets, tau, op, sector_label, n_labels, precision
                                          ctypes.byref(o), out.ctypes.data_as(ctypes.POINTER(ctr_value)),
                                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out, hist
+
+
+def ctr_density_matrix(ctx, offsets, tau, op, sector_dims, weight=None):
+    """(values [n_cfg] VALUE_DTYPE, list of per-sector complex blocks sum_C weight_C R(C))."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    tau, op = _string_arrays(tau, op)
+    n = offsets.size - 1
+    dims = [int(d) for d in sector_dims]
+    out = np.zeros(n, dtype=VALUE_DTYPE)
+    rho = np.zeros(sum(d * d for d in dims), dtype=np.complex128)
+    w = None if weight is None else np.ascontiguousarray(weight, dtype=np.complex128)
+    if w is not None and w.shape != (n,):
+        raise ValueError("one weight per configuration")
+    _check(ctx, _lib.ctr_density_matrix(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
+                                        _ptr(op, ctypes.c_int32),
+                                        w.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                        if w is not None else None,
+                                        out.ctypes.data_as(ctypes.POINTER(ctr_value)),
+                                        rho.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    blocks, o = [], 0
+    for d in dims:
+        blocks.append(rho[o:o + d * d].reshape(d, d))
+        o += d * d
+    return out, blocks
 
 
 def ctr_bound(ctx, tau, op) -> float:
@@ -610,6 +635,9 @@ class TraceContext:
     def histogram(self, offsets, tau, op, sector_label, n_labels, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO,
                   slices=0):
         return ctr_trace_histogram(self.ctx, offsets, tau, op, sector_label, n_labels, precision, kernel, slices)
+
+    def density_matrix(self, offsets, tau, op, weight=None):
+        return ctr_density_matrix(self.ctx, offsets, tau, op, self.table.dims, weight)
 
     def bound(self, tau, op) -> float:
         return ctr_bound(self.ctx, tau, op)

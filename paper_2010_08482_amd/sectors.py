@@ -36,6 +36,7 @@ class SectorTable:
     next: np.ndarray              # [n_sec, 2*n_f] int32, -1 = zero sector
     blocks: list                  # [n_sec][n_f]: annihilator block d(next[q][2f]) x d(q) or None
     states: list                  # per sector: occupation states (int64) in basis order
+    vectors: list | None = None   # per sector: eigenvectors (columns) on `states`, if kept
 
     @property
     def n_sectors(self) -> int:
@@ -128,14 +129,16 @@ def _eigh_invariant_parts(Hq: np.ndarray):
     return E[order], V[:, order]
 
 
-def build_sectors(imp, phase_seed: int | None = None, force_complex: bool = False) -> SectorTable:
+def build_sectors(imp, phase_seed: int | None = None, force_complex: bool = False,
+                  keep_vectors: bool = False) -> SectorTable:
     """Sector table of an impurity (anything with n_flavors, beta, h1, U, qn).
 
     phase_seed: multiply every eigenvector by a random phase.  Eigenvectors
     are only defined up to such phases (and up to rotations inside
     degenerate levels); traces do not depend on the choice, but the blocks
     become genuinely complex, which exercises the complex kernels even when
-    H_loc is real."""
+    H_loc is real.  keep_vectors: keep every sector's eigenvectors in the
+    table (to express sector-basis results on occupation states)."""
     nf = int(imp.n_flavors)
     D = 1 << nf
     h1 = np.asarray(imp.h1)
@@ -197,4 +200,4 @@ def build_sectors(imp, phase_seed: int | None = None, force_complex: bool = Fals
             blocks[q][f] = np.ascontiguousarray(vecs[tgt].conj().T @ CV)
     return SectorTable(nf, float(imp.beta), cplx, tuple(getattr(imp, "qn_names", ())), keys,
                        np.array([s.shape[0] for s in sec_states], dtype=np.int32), energies, nxt, blocks,
-                       sec_states)
+                       sec_states, vecs if keep_vectors else None)

@@ -185,3 +185,23 @@ def test_remove_pair_keeps_flavors_alternating():
                 assert np.all(k[1:] != k[:-1]) and k[0] != k[-1]
         # the new string is a subsequence of the old one
         assert np.all(np.isin(p.tau, s.tau))
+
+
+@pytest.mark.parametrize("name", ["kanamori2", "pshell", "pshell_cf", "dshell"])
+def test_every_nonzero_block_has_spectral_norm_one(name):
+    """Sectors by occupation-diagonal charges are spanned by occupation
+    states, so a nonzero block of c_f leaving sector q contains some state
+    with f occupied, and c+_f c_f = n_f makes its spectral norm exactly 1:
+    per-block norms cannot tighten the lazy bound below ||F|| = 1."""
+    from paper_2010_08482_amd.sectors import build_sectors
+
+    tab = build_sectors(make_impurity(name))
+    seen = 0
+    for q in range(tab.n_sectors):
+        for f in range(tab.n_flavors):
+            B = tab.blocks[q][f]
+            if B is None:
+                continue
+            assert abs(np.linalg.norm(B, 2) - 1.0) < 1e-12
+            seen += 1
+    assert seen > 10
