@@ -244,7 +244,7 @@ def cpu_baseline(imp, strings, seconds_budget=20.0):
     return len(done) / el, len(done), el, threads, done
 
 
-def cpu_oracle_extrapolated(tab, strings, probe_dim=1024):
+def cpu_oracle_extrapolated(tab, strings, probe_dim=2048):
     """The dense CPU oracle's cost on a full-size impurity, extrapolated: it
     multiplies one 2^n x 2^n matrix per operator, so a trace costs the mean
     operator count times one such product, timed here at probe_dim and scaled
@@ -267,9 +267,11 @@ def cpu_oracle_extrapolated(tab, strings, probe_dim=1024):
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") in
                    ("openblas", "mkl", "blis")] or [1])
     return {"value": 1.0 / (t_product * mean_ops), "unit": "trace evals/s", "cores": threads,
-            "kind": "oracle (extrapolated)",
-            "sample": f"one {probe_dim}^3 {'complex' if tab.is_complex else 'real'} product in {t_probe * 1e3:.1f} ms, "
-                      f"x ({D}/{probe_dim})^3 per operator, {mean_ops:.0f} operators per trace"}
+            "kind": "oracle",
+            "sample": f"extrapolated: the dense oracle's step (one {D}x{D} {'complex' if tab.is_complex else 'real'} "
+                      f"product per operator) timed at {probe_dim}^3 ({t_probe * 1e3:.1f} ms, 3 repeats) and scaled by "
+                      f"({D}/{probe_dim})^3, x {mean_ops:.0f} operators per trace (mean of the workload); one "
+                      f"2^14-state trace takes hours on the host"}
 
 
 def cpu_block_sparse(tab, strings, seconds_budget=5.0):

@@ -86,10 +86,12 @@ typedef struct {
 enum {
   CTR_KERNEL_AUTO = 0,    /* the kernel ctr_tune picked, for non-lazy FP64 batches of at least a
                              quarter of its sample; otherwise FP64 with sectors <= 128 states: the
-                             wavefront kernel; else, for batches of >= 48 FP64 traces (lazy ones
-                             included), the block-grouped rounds when the sectors fit them and the
-                             arena holds their scratch; else the LDS-resident workgroup kernel when
-                             the panel fits LDS, else streaming */
+                             wavefront kernel; else the block-grouped rounds (lazy calls included)
+                             for batches of >= 48 traces, and for any batch once a sector exceeds
+                             384 states (their row-chunked items), while the arena holds their
+                             scratch; else the LDS-resident workgroup kernel when the panel fits
+                             LDS, else streaming.  FP32-split: the grouped split items for batches
+                             of >= 48 or where the LDS kernel cannot run, else the LDS kernel */
   CTR_KERNEL_WAVE = 1,    /* one wavefront per 8-column panel; sectors <= 128 states, FP64 only */
   CTR_KERNEL_BLOCK = 2,   /* one workgroup per 16-column panel, X in LDS (<= 1024 real / 576 complex) */
   CTR_KERNEL_STREAM = 3,  /* one workgroup per 16-column panel, X in global memory; any size, FP64 only */
@@ -100,9 +102,10 @@ enum {
                              reject by the string bounds before the rounds (no refinement while strings
                              run).  Synchronises the stream once per batch (to size its scratch from
                              the number of surviving strings) */
-  CTR_KERNEL_GROUPED_ROWS = 5 /* the block-grouped rounds with work items of 64 columns x 128 rows of a
-                             block for any sector size: the per-column power of two is a device-wide
-                             maximum over the row chunks, applied when the next round loads the column */
+  CTR_KERNEL_GROUPED_ROWS = 5 /* the block-grouped rounds with work items of 32 columns x 256 rows of a
+                             block (FP32-split: 16 x 128) for any sector size: the per-column power of
+                             two is a device-wide maximum over the row chunks, applied when the next
+                             round loads the column */
 };
 
 typedef struct {
@@ -111,8 +114,17 @@ typedef struct {
                           truncation error ~256-fold for a third more FP32 products (28 instead of 21) */
   int32_t kernel;      /* CTR_KERNEL_*; a kernel that cannot run this impurity/precision
                           gives CTR_ERR_UNSUPPORTED */
-  int32_t reserved;    /* must be 0 */
+  int32_t flags;       /* CTR_OPT_* bits; 0 for the defaults */
 } ctr_opts;
+
+/* ctr_opts.flags */
+enum {
+  CTR_OPT_GRAPH = 1    /* grouped rounds: the rounds of every chunk are built into one HIP graph (one
+                          kernel node per round, each depending on the one before) and launched as one,
+                          instead of one launch per round; the graph is instantiated per chunk (the
+                          rounds and their work items depend on the batch).  Same kernels, same values;
+                          ignored by the per-string kernels */
+};
 
 /*
  * The impurity in sector form (Sec. 3.3.1): sector dimensions, the H_loc

@@ -1584,9 +1584,12 @@ GVariant make_bvariant() {
                   WR * RT * 16};
 }
 
+// FP32-split items: 8 wavefronts x one row tile x one column tile (128 rows x 16 columns); on the
+// crystal-field f-shell (16 configurations, 7 slices) 1.08 traces/s against 1.04 for 8 x 1 x 2 and 0.91 for
+// 4 x 2 wavefronts of 1 x 2 tiles (the level accumulators leave room for few tiles per wavefront)
 template <bool CPLX, int NSL>
 GVariant make_svariant() {
-  constexpr int WR = 4, WC = 2, RT = 1, CT = 2;
+  constexpr int WR = 8, WC = 1, RT = 1, CT = 1;
   return GVariant{reinterpret_cast<const void*>(&k_gbig_split<CPLX, WR, WC, RT, CT, NSL>), WR * WC, WC * CT * 16,
                   WR * RT * 16};
 }
@@ -1607,23 +1610,26 @@ bool pick_gvariant(const DevImp& imp, int alt, GVariant* v, int split = 0) {
     return alt == 2;
   }
   if (alt >= 2) {
-    // row-chunked items at any size (alt 2 and 3: the two tile shapes)
-    if (imp.is_complex) *v = alt == 3 ? make_bvariant<true, 4, 1, 2, 4>() : make_bvariant<true, 4, 2, 2, 2>();
-    else *v = alt == 3 ? make_bvariant<false, 4, 1, 2, 4>() : make_bvariant<false, 4, 2, 2, 2>();
+    // row-chunked items at any size (alt 2 and 3: the two tile shapes).  A sweep of 14 shapes on the
+    // crystal-field f-shell (200 configurations) put 16 wavefronts x one row tile x two column tiles
+    // (256 rows x 32 columns, 4 wavefronts per SIMD) first at 16.0 traces/s, 8 x 2 x 2 at 14.4,
+    // 4 x 2 column groups of 2 x 2 at 12.3; chunks of 16, 32 or 64 staged rows of X were alike
+    if (imp.is_complex) *v = alt == 3 ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2>();
+    else *v = alt == 3 ? make_bvariant<false, 8, 1, 2, 2>() : make_bvariant<false, 16, 1, 1, 2>();
     return alt <= 3;
   }
   if (imp.is_complex) {
     if (tiles <= 2) *v = make_wvariant<true, 2>();
     else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
     else if (tiles <= 24) *v = alt ? make_gvariant<true, 8, 3, 2>() : make_gvariant<true, 12, 2, 2>();
-    else *v = alt ? make_bvariant<true, 4, 1, 2, 4>() : make_bvariant<true, 4, 2, 2, 2>();
+    else *v = alt ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2>();
     return !alt || tiles > 8;
   }
   if (tiles <= 2) *v = make_wvariant<false, 2>();
   else if (tiles <= 4) *v = make_wvariant<false, 4>();
   else if (tiles <= 8) *v = alt ? make_wvariant<false, 8, 1>() : make_wvariant<false, 8, 2>();
   else if (tiles <= 24) *v = make_gvariant<false, 8, 3, 4>();
-  else *v = alt ? make_bvariant<false, 4, 1, 2, 4>() : make_bvariant<false, 4, 2, 2, 2>();
+  else *v = alt ? make_bvariant<false, 8, 1, 2, 2>() : make_bvariant<false, 16, 1, 1, 2>();
   return !alt || (tiles > 4 && tiles <= 8) || tiles > 24;
 }
 
@@ -1685,6 +1691,20 @@ hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const Group
   if (v.cw != g.cw_step || v.rchunk != g.rchunk) return hipErrorInvalidValue;  // schedule built for another shape
   void* args[] = {const_cast<DevImp*>(&imp), const_cast<BatchArgs*>(&b), const_cast<GroupArgs*>(&g), &r};
   return hipLaunchKernel(v.fn, dim3(grid), dim3(v.nw * 64), args, 0, stream);
+}
+
+hipError_t group_round_node(const DevImp& imp, const GroupArgs& g, int grid, int alt, int split, void** args,
+                            hipKernelNodeParams* p) {
+  GVariant v;
+  if (!pick_gvariant(imp, alt, &v, split) || grid <= 0) return hipErrorInvalidValue;
+  if (v.cw != g.cw_step || v.rchunk != g.rchunk) return hipErrorInvalidValue;
+  p->func = const_cast<void*>(v.fn);
+  p->gridDim = dim3(grid);
+  p->blockDim = dim3(v.nw * 64);
+  p->sharedMemBytes = 0;
+  p->kernelParams = args;
+  p->extra = nullptr;
+  return hipSuccess;
 }
 
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream) {

@@ -193,6 +193,10 @@ hipError_t launch_group_schedule(const DevImp& imp, const BatchArgs& b, const Gr
 hipError_t launch_group_round(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, int r, int grid, int alt,
                               int split, hipStream_t stream);
 hipError_t launch_group_combine(const DevImp& imp, const BatchArgs& b, const GroupArgs& g, hipStream_t stream);
+// Kernel-node parameters of round launches for a HIP graph (args: {&imp, &b, &g, &r}, kept alive by the caller
+// until the node is added).
+hipError_t group_round_node(const DevImp& imp, const GroupArgs& g, int grid, int alt, int split, void** args,
+                            hipKernelNodeParams* p);
 size_t rdm_buffer_doubles(const DevImp& imp, int slots);
 int rdm_grid(int device);
 hipError_t launch_rdm(const DevImp& imp, const BatchArgs& b, const RdmArgs& d, int grid, hipStream_t stream);

@@ -29,6 +29,7 @@ CTR_KERNEL_BLOCK = 2
 CTR_KERNEL_STREAM = 3
 CTR_KERNEL_GROUPED = 4
 CTR_KERNEL_GROUPED_ROWS = 5
+CTR_OPT_GRAPH = 1
 
 
 class ctr_value(ctypes.Structure):
@@ -39,7 +40,7 @@ class ctr_value(ctypes.Structure):
 
 class ctr_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("slices", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class ctr_impurity(ctypes.Structure):
@@ -173,11 +174,12 @@ def ctr_destroy(ctx) -> None:
     _lib.ctr_destroy(ctx)
 
 
-def _opts(precision, kernel=CTR_KERNEL_AUTO, slices=0):
+def _opts(precision, kernel=CTR_KERNEL_AUTO, slices=0, flags=0):
     o = ctr_opts()
     o.precision = int(precision)
     o.kernel = int(kernel)
     o.slices = int(slices)
+    o.flags = int(flags)
     return o
 
 
@@ -234,12 +236,12 @@ def ctr_trace(ctx, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
     return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.log_abs, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
 
 
-def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0):
+def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0, flags=0):
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     tau, op = _string_arrays(tau, op)
     n = offsets.size - 1
     out = np.zeros(n, dtype=VALUE_DTYPE)
-    o = _opts(precision, kernel, slices)
+    o = _opts(precision, kernel, slices, flags)
     _check(ctx, _lib.ctr_trace_batch(ctx, n, _ptr(offsets, ctypes.c_int64), _ptr(tau, ctypes.c_double),
                                      _ptr(op, ctypes.c_int32), ctypes.byref(o),
                                      out.ctypes.data_as(ctypes.POINTER(ctr_value))))
@@ -247,9 +249,9 @@ def ctr_trace_batch(ctx, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL
 
 
 def ctr_trace_batch_device(ctx, n_cfg, d_offsets_ptr, d_tau_ptr, d_op_ptr, d_out_ptr, precision=CTR_FP64,
-                           kernel=CTR_KERNEL_AUTO, slices=0):
+                           kernel=CTR_KERNEL_AUTO, slices=0, flags=0):
     """Device pointers (ints); enqueues on the context's stream."""
-    o = _opts(precision, kernel, slices)
+    o = _opts(precision, kernel, slices, flags)
     _check(ctx, _lib.ctr_trace_batch_device(ctx, int(n_cfg), ctypes.c_void_p(d_offsets_ptr),
                                             ctypes.c_void_p(d_tau_ptr), ctypes.c_void_p(d_op_ptr),
                                             ctypes.byref(o), ctypes.c_void_p(d_out_ptr)))
@@ -623,8 +625,8 @@ class TraceContext:
         op = np.concatenate(ops) if ops else np.zeros(0, np.int32)
         return ctr_trace_batch(self.ctx, offs, tau, op, precision, kernel, slices)
 
-    def trace_packed(self, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0):
-        return ctr_trace_batch(self.ctx, offsets, tau, op, precision, kernel, slices)
+    def trace_packed(self, offsets, tau, op, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO, slices=0, flags=0):
+        return ctr_trace_batch(self.ctx, offsets, tau, op, precision, kernel, slices, flags)
 
     def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision, kernel)

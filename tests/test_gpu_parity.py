@@ -257,6 +257,29 @@ def test_generic_fshell_low_orders_vs_golden(lib, ctx, name, kernels):
                       [(r["abs"], r["abs_log"]) for r in g["records"]], f"{name}/{k}")
 
 
+def test_fshell_workload_strings_vs_golden(lib, ctx):
+    """Workload strings of the generic f-shell (N, Jz) benchmark at production
+    order (40-44 operators) against the dense oracle (memory-bounded route,
+    stored values): every FP64 kernel that runs the impurity and FP32-split."""
+    path = os.path.join(HERE, "golden", "fshell_workload.json")
+    if not os.path.exists(path):
+        pytest.skip("fshell_workload.json not generated")
+    g = load_golden("fshell_workload")
+    tab, c = ctx(g["impurity"])
+    cfgs = make_configs(2, max(r["i"] for r in g["records"]) + 1)
+    strings = [cfgs[r["i"]] for r in g["records"]]
+    for s_, r in zip(strings, g["records"]):
+        assert s_.n == r["n"] and np.allclose(s_.tau, r["tau"]) and np.array_equal(s_.op, r["op"])
+    refs = [golden_pair(r) for r in g["records"]]
+    scales = [(r["abs"], r["abs_log"]) for r in g["records"]]
+    for k in ("block", "stream", "grouped", "grouped_rows"):
+        say(f"[gpu] fshell workload strings x{len(strings)} kernel={k}")
+        check_against(c.trace_batch(strings, kernel=HIST_KERNELS[k]), refs, scales, f"fshell workload {k}")
+    say("[gpu] fshell workload strings FP32-split")
+    check_against(c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7),
+                  refs, scales, "fshell workload fp32-split")
+
+
 # ---------------------------------------------------------------------------
 # full f-shell size: density-density impurity, exact by state enumeration
 # ---------------------------------------------------------------------------
@@ -1271,3 +1294,28 @@ def test_density_matrix_label_sums_match_histogram_dshell(lib, ctx):
             sums[n_of[q]] += np.trace(B)
         assert np.max(np.abs(sums - hist[i])) <= 1e-10 + 1e-12 * ratio, i
         assert abs(sums.sum() - 1.0) <= 1e-10 + 1e-12 * ratio
+
+
+def test_grouped_rounds_as_one_graph(lib, ctx):
+    """CTR_OPT_GRAPH: the rounds of every chunk launched as one HIP graph give
+    the values of the round-by-round launches, bit for bit, call after call
+    (eager calls in between), on the grouped wavefront, workgroup and
+    row-chunked kernels and on the FP32-split items."""
+    cases = [("dshell", make_configs(1, 300), lib.CTR_FP64, lib.CTR_KERNEL_GROUPED),
+             ("fshell", make_configs(2, 60), lib.CTR_FP64, lib.CTR_KERNEL_GROUPED),
+             ("fshell", make_configs(2, 60), lib.CTR_FP64, lib.CTR_KERNEL_GROUPED_ROWS),
+             ("pshell", None, lib.CTR_FP32_SPLIT, lib.CTR_KERNEL_GROUPED)]
+    rng = np.random.Generator(np.random.PCG64(808))
+    for name, cfgs, prec, kern in cases:
+        tab, c = ctx(name)
+        if cfgs is None:
+            cfgs = [random_string(rng, tab.n_flavors, tab.beta, 2 * int(rng.integers(0, 20)), "alternating")
+                    for _ in range(120)]
+        offs, tau, op = pack(cfgs)
+        for rep in range(3):
+            say(f"[gpu] graph vs eager rounds {name} kernel={kern} precision={prec} call {rep}")
+            e = c.trace_packed(offs, tau, op, precision=prec, kernel=kern, slices=7 if prec else 0)
+            g = c.trace_packed(offs, tau, op, precision=prec, kernel=kern, slices=7 if prec else 0,
+                               flags=lib.CTR_OPT_GRAPH)
+            for f in ("re", "im", "log_scale", "flags", "n_strings"):
+                assert np.array_equal(e[f], g[f]), (name, f, rep)
