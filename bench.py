@@ -107,6 +107,10 @@ TRAFFIC_MEASURED = {
         "source": "ctrace_kernels.hip",
         "sha256": "213e78688ec5b1bcafdd25921e57229a61c5a9489d9987da0d95e4da625eeaf7",
         "bytes": 73.0208e9},
+    ("k_gbig", "fshell-slater-soc-cf-2000-orders60-200, 200 per step"): {
+        "source": "ctrace_group.hip",
+        "sha256": "f458b6d1e0ebe63f942ac8f8f82525dfb984b8f09892ec165c47a78127a1898c",
+        "bytes": 201.881e9},
 }
 
 
@@ -349,7 +353,8 @@ def serve_main(args, emit: bool = True):
     share = [float(x) for x in args.serve_grid_share.split(",")] if args.serve_grid_share else None
     if share is not None:
         share = (share + [1.0] * len(names))[: len(names)]
-    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch, hbm_budget=budget, grid_share=share)
+    srv = ctrace.TraceServer(ctxs, max_batch=args.serve_batch, hbm_budget=budget, grid_share=share,
+                             max_pass_flop=args.serve_max_pass_gflop * 1e9)
     results = []
     lock = threading.Lock()
     busy_chain = np.zeros(n_chains, dtype=bool)
@@ -436,7 +441,8 @@ def serve_main(args, emit: bool = True):
         "config": {"workload": "serving mix: 256 Markov chains, Poisson arrivals, pair insert/remove moves, "
                                "one request in flight per chain",
                    "impurities": names, "chain_share": chain_share, "max_batch": args.serve_batch,
-                   "hbm_budget_bytes": budget, "grid_share": share, "streams": "one per impurity"},
+                   "hbm_budget_bytes": budget, "grid_share": share, "streams": "one per impurity",
+                   "max_pass_gflop": args.serve_max_pass_gflop or None},
     }
     for c in ctxs:
         c.close()
@@ -678,6 +684,8 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=4096, help="serving mix: most requests per device pass")
     ap.add_argument("--serve-grid-share", default="1,1,0.5",
                     help="serving mix: per-impurity fractions of the persistent grids ('' = full grids)")
+    ap.add_argument("--serve-max-pass-gflop", type=float, default=0.0,
+                    help="serving mix: cap on one pass's estimated block-product GFLOP (0 = no cap)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every run here has a single MI355X and the trace path has no "

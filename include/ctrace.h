@@ -489,6 +489,11 @@ typedef struct {
                            leaves slots on the device for the others' kernels; the contexts get the
                            whole device back at ctr_server_destroy.  NULL: every context launches
                            full grids */
+  double max_pass_flop;  /* cap on the estimated block-product flops of one pass (every surviving string
+                           at its narrowest width, 2 flops per multiply-add, 8 complex; host walk of the
+                           sector map): a pass stops admitting once the next request would exceed it, so
+                           long passes of a heavy impurity do not hold back requests that arrive
+                           meanwhile; at least one request is always admitted; 0 = no cap */
 } ctr_server_opts;
 
 typedef struct {

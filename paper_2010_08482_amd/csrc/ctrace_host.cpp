@@ -548,6 +548,29 @@ double context_beta(const ctr_ctx* ctx) { return ctx->beta; }
 int context_nops(const ctr_ctx* ctx) { return ctx->nops; }
 size_t context_free_scratch(const ctr_ctx* ctx) { return ctx->arena_bytes - ctx->resident; }
 void context_set_grid_share(ctr_ctx* ctx, double share) { ctx->grid_share = share; }
+double request_flops(const ctr_ctx* ctx, long long n_ops, const int32_t* op) {
+  // block products of every surviving string rotated to its narrowest sector: 2 (8 complex) flops per
+  // multiply-add, width x d_out x d_in per operator
+  const double c = ctx->imp.is_complex ? 8.0 : 2.0;
+  double total = 0.0;
+  std::vector<int> path((size_t)std::max(n_ops, 0LL) + 1);
+  for (int q0 = 0; q0 < ctx->n_sec; ++q0) {
+    int q = q0, w = ctx->h_dim[q0];
+    path[0] = q0;
+    long long i = 0;
+    for (; i < n_ops && q >= 0; ++i) {
+      q = ctx->h_next[(size_t)q * ctx->nops + op[i]];
+      path[i + 1] = q;
+      if (q >= 0) w = std::min(w, ctx->h_dim[q]);
+    }
+    if (q != q0 || i < n_ops) continue;
+    double steps = 0.0;
+    for (long long j = 0; j < n_ops; ++j) steps += (double)ctx->h_dim[path[j]] * ctx->h_dim[path[j + 1]];
+    total += c * w * steps;
+  }
+  return total;
+}
+
 size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops, const int32_t* op) {
   size_t bytes = scratch_per_cfg(ctx) + sizeof(long long) + sizeof(ctr_value) + sizeof(double) + 64 +
                  (size_t)n_ops * (sizeof(double) + sizeof(int32_t));

@@ -211,6 +211,8 @@ size_t context_free_scratch(const ctr_ctx* ctx);          // arena bytes not hel
 // Arena bytes one configuration occupies in a batch call: per-call scratch, and with the grouped
 // rounds the carried matrices of its surviving strings (host walk of the sector map).
 size_t request_scratch_bytes(const ctr_ctx* ctx, long long n_ops, const int32_t* op);
+// Block-product flops of one configuration (its surviving strings at their narrowest width; host walk).
+double request_flops(const ctr_ctx* ctx, long long n_ops, const int32_t* op);
 // Fraction in (0, 1] of every persistent grid the context launches (1 = the whole device).
 void context_set_grid_share(ctr_ctx* ctx, double share);
 

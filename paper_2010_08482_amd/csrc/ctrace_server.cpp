@@ -2,8 +2,9 @@
 //
 // One worker thread per context (impurity), each on its context's stream:
 // requests queue per impurity; when a worker's device pass ends it admits the
-// requests that arrived meanwhile, in arrival order, up to the batch limit
-// and the scratch budget, and evaluates them as one batch.  Different
+// requests that arrived meanwhile, in arrival order, up to the batch limit,
+// the scratch budget and an optional cap on the pass's estimated work, and
+// evaluates them as one batch.  Different
 // impurities' passes run concurrently on their own streams.  An optional grid
 // share per impurity launches only that fraction of each persistent grid, so
 // the workgroups of one impurity's long pass leave slots on the device where
@@ -52,6 +53,7 @@ struct ctr_server {
   std::vector<std::unique_ptr<Lane>> lanes;
   int max_batch = 1;
   int max_pending = 1;
+  double max_pass_flop = 0.0;  // 0: no cap on a pass's estimated block-product flops
   std::mutex rm;
   std::condition_variable rcv;
   std::deque<ctr_result> done;
@@ -76,10 +78,17 @@ void run_lane(ctr_server* srv, Lane* L) {
       L->cv.wait(lk, [&] { return srv->stop.load() || !L->pending.empty(); });
       if (srv->stop.load()) return;
       size_t bytes = 0;
+      double flop = 0.0;
       while (!L->pending.empty() && (int)batch.size() < srv->max_batch) {
         const Request& f = L->pending.front();
         const size_t need = ctr::request_scratch_bytes(L->ctx, (long long)f.op.size(), f.op.data());
         if (!batch.empty() && bytes + need > L->budget) break;  // admission by scratch footprint
+        if (srv->max_pass_flop > 0.0) {
+          // a cap on the pass's work keeps passes short, so requests arriving meanwhile wait less
+          const double w = ctr::request_flops(L->ctx, (long long)f.op.size(), f.op.data());
+          if (!batch.empty() && flop + w > srv->max_pass_flop) break;
+          flop += w;
+        }
         bytes += need;
         batch.push_back(std::move(L->pending.front()));
         L->pending.pop_front();
@@ -144,6 +153,7 @@ ctr_status ctr_server_create(ctr_ctx* const* ctxs, int32_t n_ctx, const ctr_serv
   ctr_server* srv = new ctr_server();
   srv->max_batch = opts->max_batch;
   srv->max_pending = opts->max_pending;
+  srv->max_pass_flop = opts->max_pass_flop > 0.0 ? opts->max_pass_flop : 0.0;
   for (int i = 0; i < n_ctx; ++i) {
     std::unique_ptr<Lane> L(new Lane());
     L->ctx = ctxs[i];

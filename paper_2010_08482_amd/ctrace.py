@@ -53,7 +53,7 @@ class ctr_impurity(ctypes.Structure):
 
 class ctr_server_opts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t),
-                ("grid_share", ctypes.POINTER(ctypes.c_double))]
+                ("grid_share", ctypes.POINTER(ctypes.c_double)), ("max_pass_flop", ctypes.c_double)]
 
 
 class ctr_mc_opts(ctypes.Structure):
@@ -381,14 +381,14 @@ def ctr_tune(ctx, offsets, tau, op):
 
 
 def ctr_server_create(ctxs, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0,
-                      grid_share=None):
+                      grid_share=None, max_pass_flop: float = 0.0):
     """grid_share: optional per-context fractions in (0, 1] of each persistent grid."""
     arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
     share = None if grid_share is None else np.ascontiguousarray(grid_share, dtype=np.float64)
     if share is not None and share.size != len(ctxs):
         raise ValueError("one grid share per context")
     o = ctr_server_opts(int(max_batch), int(max_pending), int(hbm_budget),
-                        _ptr(share, ctypes.c_double) if share is not None else None)
+                        _ptr(share, ctypes.c_double) if share is not None else None, float(max_pass_flop))
     out = ctypes.c_void_p()
     st = _lib.ctr_server_create(arr, len(ctxs), ctypes.byref(o), ctypes.byref(out))
     if st != CTR_OK:
@@ -451,9 +451,13 @@ def ctr_mc_set_config(mc, chain, tau, op):
                                         _ptr(op, ctypes.c_int32)))
 
 
-def ctr_mc_step(mc, u):
-    """u: [n_chains, 6] uniforms in [0, 1); returns the decisions (int32 [n_chains])."""
+def ctr_mc_step(mc, u, n_chains=None):
+    """u: [n_chains, 6] uniforms in [0, 1); returns the decisions (int32 [n_chains]).
+    The library reads n_chains x 6 values: a u of another shape raises ValueError
+    when n_chains is given (MarkovChains.step always passes it)."""
     u = np.ascontiguousarray(u, dtype=np.float64)
+    if u.ndim != 2 or u.shape[1] != 6 or (n_chains is not None and u.shape[0] != int(n_chains)):
+        raise ValueError(f"u must have shape (n_chains, 6), got {u.shape}")
     dec = np.zeros(u.shape[0], dtype=np.int32)
     _check(None, _lib.ctr_mc_step(mc, _ptr(u, ctypes.c_double), _ptr(dec, ctypes.c_int32)))
     return dec
@@ -499,7 +503,7 @@ class MarkovChains:
         ctr_mc_set_config(self.mc, chain, tau, op)
 
     def step(self, u):
-        return ctr_mc_step(self.mc, u)
+        return ctr_mc_step(self.mc, u, self.n_chains)
 
     def config(self, chain):
         return ctr_mc_config(self.mc, chain)
@@ -526,10 +530,10 @@ class TraceServer:
     """Continuous-batching server over TraceContexts (one worker per context)."""
 
     def __init__(self, contexts, max_batch: int = 4096, max_pending: int = 1 << 20, hbm_budget: int = 0,
-                 grid_share=None):
+                 grid_share=None, max_pass_flop: float = 0.0):
         self.contexts = list(contexts)
         self.srv = ctr_server_create([c.ctx for c in self.contexts], max_batch, max_pending, hbm_budget,
-                                     grid_share)
+                                     grid_share, max_pass_flop)
 
     def submit(self, impurity, tag, tau, op, log_threshold=-math.inf):
         return ctr_server_submit(self.srv, impurity, tag, tau, op, log_threshold)

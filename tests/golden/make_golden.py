@@ -118,6 +118,10 @@ SETS = {
     # cheapest for the dense oracle among its first 400 configurations of order <= 44)
     "fshell_workload": lambda: workload_set("fshell_workload", "fshell", 2, [93, 391],
                                             os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell")),
+    # a production-order string of the crystal-field f-shell benchmark (order 60, its lowest; the
+    # cheapest for the dense oracle among the 26 of order 60 in its 2000 configurations)
+    "fshell_cf_workload": lambda: workload_set("fshell_cf_workload", "fshell_cf", 3, [480],
+                                               os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell_cf")),
 }
 
 if __name__ == "__main__":

@@ -89,3 +89,15 @@ def test_binding_struct_layouts_match_header(tmp_path):
         assert got[(s, "size")] == ctypes.sizeof(st), s
         for name, _ in st._fields_:
             assert got[(s, name)] == getattr(st, name).offset, (s, name)
+
+
+def test_markov_step_rejects_uniforms_of_the_wrong_shape():
+    """The library reads n_chains x 6 uniforms: the binding refuses any other
+    shape before the call (no chain set is needed to see it)."""
+    import numpy as np
+
+    from paper_2010_08482_amd import ctrace
+
+    for shape in [(4, 5), (3, 6), (24,)]:
+        with pytest.raises(ValueError):
+            ctrace.ctr_mc_step(None, np.zeros(shape), n_chains=4)

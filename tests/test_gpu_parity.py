@@ -257,27 +257,32 @@ def test_generic_fshell_low_orders_vs_golden(lib, ctx, name, kernels):
                       [(r["abs"], r["abs_log"]) for r in g["records"]], f"{name}/{k}")
 
 
-def test_fshell_workload_strings_vs_golden(lib, ctx):
-    """Workload strings of the generic f-shell (N, Jz) benchmark at production
-    order (40-44 operators) against the dense oracle (memory-bounded route,
-    stored values): every FP64 kernel that runs the impurity and FP32-split."""
-    path = os.path.join(HERE, "golden", "fshell_workload.json")
+@pytest.mark.parametrize("name,config_id,kernels",
+                         [("fshell_workload", 2, ("block", "stream", "grouped", "grouped_rows")),
+                          ("fshell_cf_workload", 3, ("stream", "grouped_rows"))])
+def test_fshell_workload_strings_vs_golden(lib, ctx, name, config_id, kernels):
+    """Workload strings of the generic f-shell benchmarks at production order
+    (orders 40-44 of the (N, Jz) impurity, 60 of the crystal-field one)
+    against the dense oracle (memory-bounded route, stored values): every
+    FP64 kernel that runs the impurity, and FP32-split."""
+    path = os.path.join(HERE, "golden", name + ".json")
     if not os.path.exists(path):
-        pytest.skip("fshell_workload.json not generated")
-    g = load_golden("fshell_workload")
+        pytest.skip(f"{name}.json not generated")
+    g = load_golden(name)
+    assert g["config_id"] == config_id
     tab, c = ctx(g["impurity"])
-    cfgs = make_configs(2, max(r["i"] for r in g["records"]) + 1)
+    cfgs = make_configs(config_id, max(r["i"] for r in g["records"]) + 1)
     strings = [cfgs[r["i"]] for r in g["records"]]
     for s_, r in zip(strings, g["records"]):
         assert s_.n == r["n"] and np.allclose(s_.tau, r["tau"]) and np.array_equal(s_.op, r["op"])
     refs = [golden_pair(r) for r in g["records"]]
     scales = [(r["abs"], r["abs_log"]) for r in g["records"]]
-    for k in ("block", "stream", "grouped", "grouped_rows"):
-        say(f"[gpu] fshell workload strings x{len(strings)} kernel={k}")
-        check_against(c.trace_batch(strings, kernel=HIST_KERNELS[k]), refs, scales, f"fshell workload {k}")
-    say("[gpu] fshell workload strings FP32-split")
+    for k in kernels:
+        say(f"[gpu] {name} strings x{len(strings)} kernel={k}")
+        check_against(c.trace_batch(strings, kernel=HIST_KERNELS[k]), refs, scales, f"{name} {k}")
+    say(f"[gpu] {name} strings FP32-split")
     check_against(c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7),
-                  refs, scales, "fshell workload fp32-split")
+                  refs, scales, f"{name} fp32-split")
 
 
 # ---------------------------------------------------------------------------
@@ -772,6 +777,33 @@ def test_server_results_match_alone(lib, ctx, own_streams, grid_share, cf):
     # contexts are usable again after the server is gone
     v = cd.trace(reqs[1][1].tau, reqs[1][1].op)
     assert np.array_equal(v["re"], alone[1]["re"])
+
+
+def test_server_pass_cap_admits_one_request_per_pass(lib, ctx):
+    """A cap on a pass's estimated work below any single request's: every pass
+    still admits one request (never none), and the values are unchanged."""
+    tab, c = ctx("dshell")
+    configs = make_configs(1, 40)
+    alone = [c.trace(s.tau, s.op) for s in configs]
+    srv = lib.TraceServer([c], max_batch=64, max_pass_flop=1.0)
+    try:
+        for j, s in enumerate(configs):
+            while srv.submit(0, j, s.tau, s.op) == lib.CTR_ERR_BUSY:
+                pass
+        srv.drain()
+        res = srv.poll(max_results=100)
+        passes, evaluated = srv.stats()
+    finally:
+        srv.close()
+    assert len(res) == len(configs) and evaluated == len(configs) and passes == len(configs)
+    assert np.all(res["batch"] == 1) and np.all(res["status"] == 0)
+    for r in res:
+        j = int(r["tag"])
+        got, ref = r["value"], alone[j]
+        if ref["re"] == 0 and ref["im"] == 0:
+            assert got["re"] == 0 and got["im"] == 0
+            continue
+        assert close_enough(pair(got), pair(ref), (1.0, max(float(got["log_abs"]), float(ref["log_abs"])))), j
 
 
 def test_server_rejects_invalid_and_reports_busy(lib, ctx):
