@@ -277,12 +277,20 @@ def test_fshell_workload_strings_vs_golden(lib, ctx, name, config_id, kernels):
         assert s_.n == r["n"] and np.allclose(s_.tau, r["tau"]) and np.array_equal(s_.op, r["op"])
     refs = [golden_pair(r) for r in g["records"]]
     scales = [(r["abs"], r["abs_log"]) for r in g["records"]]
+    assert all(r[0] != 0 for r in refs)
+    # at these orders the Lehmann modulus sum is 10^13-10^15 times |w|, which makes its
+    # 1e-12 A bar looser than |w| itself: hold every value to 1e-10 of |w| as well
+    outs = {}
     for k in kernels:
         say(f"[gpu] {name} strings x{len(strings)} kernel={k}")
-        check_against(c.trace_batch(strings, kernel=HIST_KERNELS[k]), refs, scales, f"{name} {k}")
+        outs[k] = c.trace_batch(strings, kernel=HIST_KERNELS[k])
     say(f"[gpu] {name} strings FP32-split")
-    check_against(c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED, slices=7),
-                  refs, scales, f"{name} fp32-split")
+    outs["fp32-split"] = c.trace_batch(strings, precision=lib.CTR_FP32_SPLIT, kernel=lib.CTR_KERNEL_GROUPED,
+                                       slices=7)
+    for k, out in outs.items():
+        check_against(out, refs, scales, f"{name} {k}")
+        for v, ref in zip(out, refs):
+            assert rel_err(pair(v), ref) <= 1e-10, (k, rel_err(pair(v), ref))
 
 
 # ---------------------------------------------------------------------------
