@@ -274,6 +274,14 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx *ctx, int32_t n_cfg, const int64_t *offs
                                 ctr_value *out);
 
 /*
+ * One lazy trace (Sec. 3.3.1): ctr_trace_lazy_batch of the single
+ * configuration (tau[n_ops], op[n_ops], host arrays) against log_threshold;
+ * *out as there.  Same arguments and errors as ctr_trace.
+ */
+ctr_status ctr_trace_lazy(ctr_ctx *ctx, int32_t n_ops, const double *tau, const int32_t *op, double log_threshold,
+                          const ctr_opts *opts, ctr_value *out);
+
+/*
  * Histogram of a conserved sector label (Sec. 2.3.2, the estimator of the
  * impurity density matrix, tau-integrated, summed over the states of every
  * label; Sec. 4.2, the valence histogram over N).  For configuration c and

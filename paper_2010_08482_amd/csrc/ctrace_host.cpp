@@ -995,6 +995,13 @@ ctr_status ctr_trace_lazy_batch(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offs
   return host_batch(ctx, n_cfg, offsets, tau, op, log_threshold, out, nullptr, 0, split, kind);
 }
 
+ctr_status ctr_trace_lazy(ctr_ctx* ctx, int32_t n_ops, const double* tau, const int32_t* op, double log_threshold,
+                          const ctr_opts* opts, ctr_value* out) {
+  if (n_ops < 0) return fail(ctx, CTR_ERR_ARG, "n_ops < 0");
+  const int64_t offs[2] = {0, n_ops};
+  return ctr_trace_lazy_batch(ctx, 1, offs, tau, op, &log_threshold, opts, out);
+}
+
 ctr_status ctr_trace_histogram(ctr_ctx* ctx, int32_t n_cfg, const int64_t* offsets, const double* tau,
                                const int32_t* op, const int32_t* sector_label, int32_t n_labels,
                                const ctr_opts* opts, ctr_value* out, double* hist) {

@@ -99,6 +99,7 @@ def _load():
         "ctr_trace_batch_device_static": (ctypes.c_int, [vp, i32, vp, vp, vp, P(ctr_opts), vp]),
         "ctr_trace_lazy_batch": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(f64), P(ctr_opts),
                                                 P(ctr_value)]),
+        "ctr_trace_lazy": (ctypes.c_int, [vp, i32, P(f64), P(i32), f64, P(ctr_opts), P(ctr_value)]),
         "ctr_trace_histogram": (ctypes.c_int, [vp, i32, P(i64), P(f64), P(i32), P(i32), i32, P(ctr_opts),
                                                P(ctr_value), P(f64)]),
         "ctr_bound": (ctypes.c_int, [vp, i32, P(f64), P(i32), P(f64)]),
@@ -277,6 +278,15 @@ def ctr_trace_lazy_batch(ctx, offsets, tau, op, log_threshold, precision=CTR_FP6
                                           _ptr(op, ctypes.c_int32), _ptr(thr, ctypes.c_double), ctypes.byref(o),
                                           out.ctypes.data_as(ctypes.POINTER(ctr_value))))
     return out
+
+
+def ctr_trace_lazy(ctx, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+    tau, op = _string_arrays(tau, op)
+    v = ctr_value()
+    o = _opts(precision, kernel)
+    _check(ctx, _lib.ctr_trace_lazy(ctx, int(op.size), _ptr(tau, ctypes.c_double), _ptr(op, ctypes.c_int32),
+                                    float(log_threshold), ctypes.byref(o), ctypes.byref(v)))
+    return np.array([(v.re, v.im, v.log_scale, v.log_bound, v.log_abs, v.n_strings, v.flags)], dtype=VALUE_DTYPE)[0]
 
 
 def ctr_trace_histogram(ctx, offsets, tau, op, sector_label, n_labels, precision=CTR_FP64,
@@ -634,6 +644,9 @@ class TraceContext:
 
     def lazy_batch(self, offsets, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
         return ctr_trace_lazy_batch(self.ctx, offsets, tau, op, log_threshold, precision, kernel)
+
+    def lazy(self, tau, op, log_threshold, precision=CTR_FP64, kernel=CTR_KERNEL_AUTO):
+        return ctr_trace_lazy(self.ctx, tau, op, log_threshold, precision, kernel)
 
     def tune(self, offsets, tau, op):
         return ctr_tune(self.ctx, offsets, tau, op)

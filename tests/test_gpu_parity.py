@@ -504,6 +504,12 @@ def test_lazy_bound_and_rejection(lib, ctx):
     # no false rejection: a rejected trace is truly below its threshold
     assert np.all(la[rej] < thr[rej])
     assert np.all(out["re"][rej] == 0)
+    # the single-configuration call gives the batch's decision and value
+    for i in range(0, 300, 37):
+        one = c.lazy(cfgs[i].tau, cfgs[i].op, thr[i])
+        assert (one["flags"] & 2) == (out["flags"][i] & 2), i
+        if not rej[i]:
+            assert close_enough(pair(one), pair(out[i]), (1.0, float(out["log_abs"][i]))), i
 
 
 @pytest.mark.parametrize("name,cid,count,kernel,split", [
