@@ -77,3 +77,30 @@ def test_unchanged_proposal_costs_only_the_closing_trace():
     c = P.proposal_costs(tab, s.tau, s.op, old, s.tau, s.op)
     assert c["panel"] == sum(int(tab.dims[p[0]]) * int(tab.dims[p[0]]) for _, p in old)
     assert c["tree"] == 0 and c["panel_accept"] == c["full"] > c["panel"]
+
+
+@pytest.mark.parametrize("name,cid,count", [("kanamori2", 0, 40), ("pshell_cf", None, 12), ("dshell", 1, 4)])
+def test_block_reference_matches_the_oracle(name, cid, count):
+    """The NumPy block-sparse reference (the bench's CPU block-sparse
+    baseline, tests/blockref.py) against the oracle's dense trace."""
+    from tests.blockref import block_trace
+    from workloads import make_configs
+
+    imp = make_impurity(name)
+    tab = build_sectors(imp)
+    dt = DenseTrace(imp)
+    if cid is None:
+        rng = np.random.Generator(np.random.PCG64(17))
+        strings = [random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 15)), "alternating")
+                   for _ in range(count)]
+    else:
+        strings = make_configs(cid, count)
+    nonzero = 0
+    for s in strings:
+        got, ref = block_trace(tab, s.tau, s.op), dt.trace(s.tau, s.op)
+        if ref[0] == 0:
+            assert got[0] == 0
+            continue
+        assert close_enough(got, ref, dt.abs_scale(s.tau, s.op))
+        nonzero += 1
+    assert nonzero >= count // 3
