@@ -111,6 +111,10 @@ TRAFFIC_MEASURED = {
         "source": "ctrace_group.hip",
         "sha256": "f458b6d1e0ebe63f942ac8f8f82525dfb984b8f09892ec165c47a78127a1898c",
         "bytes": 201.881e9},
+    ("k_gstep", "fshell-slater-soc-10^4-orders40-160, 10000 per step"): {
+        "source": "ctrace_group.hip",
+        "sha256": "f458b6d1e0ebe63f942ac8f8f82525dfb984b8f09892ec165c47a78127a1898c",
+        "bytes": 26.314e9},
 }
 
 
