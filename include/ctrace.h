@@ -136,9 +136,10 @@ enum {
  *  n_sectors     number of sectors
  *  is_complex    0: blocks are float64; 1: blocks are complex128 (interleaved re, im)
  *  sector_dim    [n_sectors] sector dimensions (>= 1)
- *  energies      [sum(sector_dim)] eigenvalues, sector after sector, each
- *                sector ascending; unshifted (the library subtracts the global
- *                minimum and folds it into log_scale)
+ *  energies      [sum(sector_dim)] eigenvalues, sector after sector, in the
+ *                order of that sector's basis (any order); unshifted (the
+ *                library subtracts the global minimum and folds it into
+ *                log_scale)
  *  next          [n_sectors * 2*n_flavors] row-major, next[q*2nf + op] = sector
  *                reached from q by operator op, or -1 (zero sector).  Must be
  *                consistent: next[q][2f+1] = p  <=>  next[p][2f] = q.

@@ -740,6 +740,8 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
       rexp_n += ctr::pad16(dim[t]);
     }
   std::vector<short> rexp((size_t)std::max(rexp_n, 1LL), 0);
+  // nonzero 16 x 4 tiles of the blocks the wavefront kernel can run (at most 8 row tiles, 32 k-steps)
+  std::vector<unsigned int> tmask((size_t)ns * nops * 8, 0xffffffffu);
 
   Bump b{ctx->arena, 0, ctx->arena_bytes};
   ctx->counter = (unsigned int*)b.take(sizeof(unsigned int));
@@ -753,8 +755,9 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   long long* d_roff = (long long*)b.take((size_t)ns * nops * sizeof(long long));
   short* d_rexp = (short*)b.take(rexp.size() * sizeof(short));
   double* d_pool = (double*)b.take((size_t)std::max(pool_doubles, 1LL) * sizeof(double));
+  unsigned int* d_tmask = (unsigned int*)b.take(tmask.size() * sizeof(unsigned int));
   if (!ctx->counter || !d_dim || !d_next || !d_boff || !d_emin || !d_eoff || !d_esh || !d_lognorm || !d_pool ||
-      !d_roff || !d_rexp)
+      !d_roff || !d_rexp || !d_tmask)
     return fail(ctx, CTR_ERR_OOM, "arena too small for the impurity (" +
                                       std::to_string((pool_doubles * 8) >> 20) + " MiB of blocks)");
   HIP_TRY(ctx, hipMemcpyAsync(d_dim, dim.data(), ns * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
@@ -816,12 +819,23 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
         if (mx > 0.0) std::frexp(mx, &ex);  // mx < 2^ex
         rexp[roff[q * nops + o] + m] = (short)std::max(-30000, std::min(30000, ex));
       }
+      if (ld <= 128 && kp <= 128) {
+        unsigned int* w = tmask.data() + (size_t)(q * nops + o) * 8;
+        for (int tt = 0; tt < 8; ++tt) w[tt] = 0u;
+        for (int k = 0; k < kp; ++k)
+          for (int m = 0; m < ld; ++m) {
+            const size_t a = (size_t)k * ld + m;
+            if (stage[a] != 0.0 || (cplx && stage[plane + a] != 0.0)) w[m >> 4] |= 1u << (k >> 2);
+          }
+      }
       HIP_TRY(ctx, hipMemcpyAsync(d_pool + boff[q * nops + o], stage.data(), stage.size() * sizeof(double),
                                   hipMemcpyHostToDevice, ctx->stream));
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     }
   HIP_TRY(ctx, hipMemcpyAsync(d_roff, roff.data(), roff.size() * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(d_rexp, rexp.data(), rexp.size() * sizeof(short), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(d_tmask, tmask.data(), tmask.size() * sizeof(unsigned int), hipMemcpyHostToDevice,
+                              ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
   ctx->imp.n_sec = ns;
@@ -841,6 +855,7 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->imp.pool = d_pool;
   ctx->imp.roff = d_roff;
   ctx->imp.rexp = d_rexp;
+  ctx->imp.tmask = d_tmask;
   ctx->h_dim = dim;
   ctx->h_next = next;
   ctx->n_sec = ns;

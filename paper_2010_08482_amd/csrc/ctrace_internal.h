@@ -36,6 +36,10 @@ struct DevImp {
   const long long* roff;     // [n_sec * nops] offset of the block's row exponents in rexp
   const short* rexp;         // per block and padded row: e with max_k |F[m][k]| < 2^e (FP32-split scaling)
   const double* pool;        // operator blocks
+  // [n_sec * nops * 8] nonzero 16 x 4 tiles of blocks of at most 128 x 128: word 8 * (q * nops + op) + t
+  // has bit c set iff rows 16 t .. 16 t + 15, columns 4 c .. 4 c + 3 hold a nonzero (either plane);
+  // all bits set for larger blocks
+  const unsigned int* tmask;
 };
 // Block (q, op) with d_out = dim[next[q][op]], d_in = dim[q] is stored column-major:
 // element (row m, column k) at pool[boff + k * pad16(d_out) + m], columns padded to pad4(d_in),

@@ -1061,37 +1061,58 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
             }
           }
         } else {
-          const int ksteps = (d_in + 3) >> 2;
-          for (int kc = 0; kc < ksteps; ++kc) {
-            const int krow = kc * 4 + lq;
-            double ar[kWaveTiles], ai[kWaveTiles];
+          // only the 16 x 4 tiles of the block that hold a nonzero are multiplied
+          // (the others add exact zeros): row tile by row tile, its nonzero
+          // k-steps in ascending order (the accumulation order of the dense
+          // loop), four at a time so that their loads are in flight together.
+          // The block's masks are wavefront-uniform.
+          const int blk = __builtin_amdgcn_readfirstlane(s * I.nops + s_op[t]);
+          const unsigned int* tm = I.tmask + (long long)blk * kWaveTiles;
 #pragma unroll
-            for (int tt = 0; tt < kWaveTiles; ++tt) {
-              if (tt < ntiles) {
-                const long long a = (long long)krow * ld + tt * 16 + ln;
-                ar[tt] = Fr[a];
-                ai[tt] = CPLX ? Fi[a] : 0.0;
-              }
-            }
-            const double b0r = Xr[krow * kWavePanel + l3];
-            const double b1r = Xr[krow * kWavePanel + 4 + l3];
-            const double b0i = CPLX ? Xi[krow * kWavePanel + l3] : 0.0;
-            const double b1i = CPLX ? Xi[krow * kWavePanel + 4 + l3] : 0.0;
+          for (int tt = 0; tt < kWaveTiles; ++tt) {
+            if (tt >= ntiles) continue;
+            unsigned int m = tm[tt];
+            while (m) {
+              int kq[4];
+              int nb = 0;
 #pragma unroll
-            for (int tt = 0; tt < kWaveTiles; ++tt) {
-              if (tt < ntiles) {
-                acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b0r, acc_r[tt][0], 0, 0, 0);
-                if (CPLX) {
-                  acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[tt], b0i, acc_r[tt][0], 0, 0, 0);
-                  acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b0i, acc_i[tt][0], 0, 0, 0);
-                  acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[tt], b0r, acc_i[tt][0], 0, 0, 0);
+              for (int j2 = 0; j2 < 4; ++j2) {
+                kq[j2] = m ? __builtin_ctz(m) : 0;
+                if (m) {
+                  m &= m - 1;
+                  ++nb;
                 }
-                if (G > 1) {
-                  acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b1r, acc_r[tt][1], 0, 0, 0);
+              }
+              double ar[4], ai[4], b0r[4], b1r[4], b0i[4], b1i[4];
+#pragma unroll
+              for (int j2 = 0; j2 < 4; ++j2) {
+                if (j2 < nb) {
+                  const int krow = kq[j2] * 4 + lq;
+                  const long long a = (long long)krow * ld + tt * 16 + ln;
+                  ar[j2] = Fr[a];
+                  ai[j2] = CPLX ? Fi[a] : 0.0;
+                  b0r[j2] = Xr[krow * kWavePanel + l3];
+                  b1r[j2] = Xr[krow * kWavePanel + 4 + l3];
+                  b0i[j2] = CPLX ? Xi[krow * kWavePanel + l3] : 0.0;
+                  b1i[j2] = CPLX ? Xi[krow * kWavePanel + 4 + l3] : 0.0;
+                }
+              }
+#pragma unroll
+              for (int j2 = 0; j2 < 4; ++j2) {
+                if (j2 < nb) {
+                  acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j2], b0r[j2], acc_r[tt][0], 0, 0, 0);
                   if (CPLX) {
-                    acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[tt], b1i, acc_r[tt][1], 0, 0, 0);
-                    acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[tt], b1i, acc_i[tt][1], 0, 0, 0);
-                    acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[tt], b1r, acc_i[tt][1], 0, 0, 0);
+                    acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[j2], b0i[j2], acc_r[tt][0], 0, 0, 0);
+                    acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j2], b0i[j2], acc_i[tt][0], 0, 0, 0);
+                    acc_i[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[j2], b0r[j2], acc_i[tt][0], 0, 0, 0);
+                  }
+                  if (G > 1) {
+                    acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j2], b1r[j2], acc_r[tt][1], 0, 0, 0);
+                    if (CPLX) {
+                      acc_r[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(-ai[j2], b1i[j2], acc_r[tt][1], 0, 0, 0);
+                      acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j2], b1i[j2], acc_i[tt][1], 0, 0, 0);
+                      acc_i[tt][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[j2], b1r[j2], acc_i[tt][1], 0, 0, 0);
+                    }
                   }
                 }
               }

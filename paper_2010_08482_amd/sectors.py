@@ -32,7 +32,7 @@ class SectorTable:
     qn_names: tuple
     labels: np.ndarray            # [n_sec, n_qn] int64, sorted lexicographically
     dims: np.ndarray              # [n_sec] int32
-    energies: list                # per sector: ascending eigenvalues (float64)
+    energies: list                # per sector: eigenvalues (float64), grouped by invariant part of H
     next: np.ndarray              # [n_sec, 2*n_f] int32, -1 = zero sector
     blocks: list                  # [n_sec][n_f]: annihilator block d(next[q][2f]) x d(q) or None
     states: list                  # per sector: occupation states (int64) in basis order
@@ -50,7 +50,7 @@ class SectorTable:
         return {tuple(int(v) for v in row): q for q, row in enumerate(self.labels)}
 
     def e0(self) -> float:
-        return float(min(e[0] for e in self.energies))
+        return float(min(float(np.min(e)) for e in self.energies))
 
 
 def _popcount_table(nf: int) -> np.ndarray:
@@ -101,8 +101,9 @@ def _hamiltonian_coo(h1, U, nf, pc):
 
 def _eigh_invariant_parts(Hq: np.ndarray):
     """Eigenpairs of one sector block, computed separately on every connected
-    component of the block's nonzero pattern and assembled (energies
-    ascending).
+    component of the block's nonzero pattern and assembled part after part
+    (parts in the order of their lowest occupation state, energies ascending
+    inside each part).
 
     H_loc often conserves more than the charges that label sectors (the
     Kanamori form, for instance, keeps the set of singly occupied orbitals).
@@ -111,7 +112,10 @@ def _eigh_invariant_parts(Hq: np.ndarray):
     carry ~1e-16 entries where the exact ones vanish, and at low temperature
     the propagators can amplify such a forbidden path by far more than
     1e16.  Solving each invariant part on its own keeps those entries exactly
-    zero."""
+    zero.  Keeping the eigenvectors of one part together keeps those zeros in
+    contiguous ranges of the operator blocks, so whole 16 x 4 tiles of the
+    MFMA products vanish and the kernels skip them (on the Kanamori d-shell
+    70% of the tiles of the large blocks)."""
     d = Hq.shape[0]
     n_comp, comp = connected_components(sp.csr_matrix(Hq != 0), directed=False)
     if n_comp == 1:
@@ -125,8 +129,7 @@ def _eigh_invariant_parts(Hq: np.ndarray):
         E[pos:pos + idx.size] = e
         V[idx, pos:pos + idx.size] = v
         pos += idx.size
-    order = np.argsort(E, kind="stable")
-    return E[order], V[:, order]
+    return E, V
 
 
 def build_sectors(imp, phase_seed: int | None = None, force_complex: bool = False,

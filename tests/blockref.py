@@ -23,7 +23,7 @@ def block_trace(tab, tau, op):
         prev = 0.0
         ok = True
         for t, o in zip(tau, op):
-            emin = tab.energies[q][0]
+            emin = float(np.min(tab.energies[q]))
             X = np.exp(-(t - prev) * (tab.energies[q] - emin))[:, None] * X
             shift += (t - prev) * (emin - E0)
             f, dag = int(o) // 2, int(o) % 2
@@ -44,7 +44,7 @@ def block_trace(tab, tau, op):
             prev = float(t)
         if not ok or q != q0:
             continue
-        emin = tab.energies[q][0]
+        emin = float(np.min(tab.energies[q]))
         X = np.exp(-(beta - prev) * (tab.energies[q] - emin))[:, None] * X
         shift += (beta - prev) * (emin - E0)
         total.append((np.trace(X), e2 * math.log(2.0) - shift - beta * E0))
