@@ -105,8 +105,8 @@ def kernel_name(tab, kernel, slices):
 TRAFFIC_MEASURED = {
     ("k_chain_wave", "dshell-kanamori-10^4-orders20-80, 10000 per step"): {
         "source": "ctrace_kernels.hip",
-        "sha256": "213e78688ec5b1bcafdd25921e57229a61c5a9489d9987da0d95e4da625eeaf7",
-        "bytes": 73.0208e9},
+        "sha256": "58f449d86ebf101b1bae33381c544f9b7a247a81f9fec35e78d5729a8068407d",
+        "bytes": 1.1833e9},
     ("k_gbig", "fshell-slater-soc-cf-2000-orders60-200, 200 per step"): {
         "source": "ctrace_group.hip",
         "sha256": "f458b6d1e0ebe63f942ac8f8f82525dfb984b8f09892ec165c47a78127a1898c",

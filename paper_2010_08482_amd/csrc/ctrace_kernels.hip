@@ -912,6 +912,7 @@ __global__ __launch_bounds__(NW * 64) void k_chain(DevImp I, BatchArgs B) {
 // B[k l/16][col l%4] and D[row 4*((l%16)/4) + l/16][col l%4].
 constexpr int kWavePanel = 8;
 constexpr int kWaveTiles = 8;  // 16-row tiles per wavefront: sectors up to 128 states
+constexpr int kTileBatch = 4;  // nonzero k-steps of one row tile loaded together
 
 template <bool CPLX>
 __host__ __device__ constexpr size_t wave_region_bytes(int xr) {
@@ -1064,7 +1065,7 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
           // only the 16 x 4 tiles of the block that hold a nonzero are multiplied
           // (the others add exact zeros): row tile by row tile, its nonzero
           // k-steps in ascending order (the accumulation order of the dense
-          // loop), four at a time so that their loads are in flight together.
+          // loop), kTileBatch at a time so that their loads are in flight together.
           // The block's masks are wavefront-uniform.
           const int blk = __builtin_amdgcn_readfirstlane(s * I.nops + s_op[t]);
           const unsigned int* tm = I.tmask + (long long)blk * kWaveTiles;
@@ -1073,19 +1074,19 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
             if (tt >= ntiles) continue;
             unsigned int m = tm[tt];
             while (m) {
-              int kq[4];
+              int kq[kTileBatch];
               int nb = 0;
 #pragma unroll
-              for (int j2 = 0; j2 < 4; ++j2) {
+              for (int j2 = 0; j2 < kTileBatch; ++j2) {
                 kq[j2] = m ? __builtin_ctz(m) : 0;
                 if (m) {
                   m &= m - 1;
                   ++nb;
                 }
               }
-              double ar[4], ai[4], b0r[4], b1r[4], b0i[4], b1i[4];
+              double ar[kTileBatch], ai[kTileBatch], b0r[kTileBatch], b1r[kTileBatch], b0i[kTileBatch], b1i[kTileBatch];
 #pragma unroll
-              for (int j2 = 0; j2 < 4; ++j2) {
+              for (int j2 = 0; j2 < kTileBatch; ++j2) {
                 if (j2 < nb) {
                   const int krow = kq[j2] * 4 + lq;
                   const long long a = (long long)krow * ld + tt * 16 + ln;
@@ -1098,7 +1099,7 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
                 }
               }
 #pragma unroll
-              for (int j2 = 0; j2 < 4; ++j2) {
+              for (int j2 = 0; j2 < kTileBatch; ++j2) {
                 if (j2 < nb) {
                   acc_r[tt][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[j2], b0r[j2], acc_r[tt][0], 0, 0, 0);
                   if (CPLX) {
