@@ -981,7 +981,7 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
     const StrRec R = recs[lo];
     const int col0 = (local - R.loc_off) * kWavePanel;
     const int ncols = min(kWavePanel, R.width - col0);
-    const int G = (ncols + 3) >> 2;
+    const int G = __builtin_amdgcn_readfirstlane((ncols + 3) >> 2);  // column groups of four, uniform
     const long long base = B.offsets[c];
     const int n = (int)(B.offsets[c + 1] - base);
     const double* tau = B.tau + base;
@@ -1032,6 +1032,11 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
         const double* Fr = I.pool + boff_next;
         const double* Fi = Fr + (long long)ld * ((d_in + 3) & ~3);
         boff_next = I.boff[s2 * I.nops + s_op[t + 1]];
+        // nonzero-tile masks of this step's block, loaded before the propagator
+        // work below so that their latency is hidden behind it
+        const uint4* tmv = (const uint4*)(I.tmask + (long long)__builtin_amdgcn_readfirstlane(s * I.nops + s_op[t]) *
+                                                         kWaveTiles);
+        const uint4 mlo = tmv[0], mhi = tmv[1];
         const int p1 = (R.jstar + t + 1) % n;  // position in front of the next operator
         const double dt2 = p1 ? tau[p1] - tau[p1 - 1] : tau[0] + I.beta - tau[n - 1];
         {
@@ -1067,19 +1072,23 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
           // k-steps in ascending order (the accumulation order of the dense
           // loop), kTileBatch at a time so that their loads are in flight together.
           // The block's masks are wavefront-uniform.
-          const int blk = __builtin_amdgcn_readfirstlane(s * I.nops + s_op[t]);
-          const unsigned int* tm = I.tmask + (long long)blk * kWaveTiles;
+          const unsigned int mw[kWaveTiles] = {mlo.x, mlo.y, mlo.z, mlo.w, mhi.x, mhi.y, mhi.z, mhi.w};
 #pragma unroll
           for (int tt = 0; tt < kWaveTiles; ++tt) {
             if (tt >= ntiles) continue;
-            unsigned int m = tm[tt];
+            unsigned int m = __builtin_amdgcn_readfirstlane(mw[tt]);
             while (m) {
+              // the batch's k-steps; unused slots repeat the first one, so that
+              // every load of the batch is issued together (and stays in bounds)
               int kq[kTileBatch];
-              int nb = 0;
+              kq[0] = __builtin_ctz(m);
+              m &= m - 1;
+              int nb = 1;
 #pragma unroll
-              for (int j2 = 0; j2 < kTileBatch; ++j2) {
-                kq[j2] = m ? __builtin_ctz(m) : 0;
+              for (int j2 = 1; j2 < kTileBatch; ++j2) {
+                kq[j2] = kq[0];
                 if (m) {
+                  kq[j2] = __builtin_ctz(m);
                   m &= m - 1;
                   ++nb;
                 }
@@ -1087,16 +1096,14 @@ __global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, Batc
               double ar[kTileBatch], ai[kTileBatch], b0r[kTileBatch], b1r[kTileBatch], b0i[kTileBatch], b1i[kTileBatch];
 #pragma unroll
               for (int j2 = 0; j2 < kTileBatch; ++j2) {
-                if (j2 < nb) {
-                  const int krow = kq[j2] * 4 + lq;
-                  const long long a = (long long)krow * ld + tt * 16 + ln;
-                  ar[j2] = Fr[a];
-                  ai[j2] = CPLX ? Fi[a] : 0.0;
-                  b0r[j2] = Xr[krow * kWavePanel + l3];
-                  b1r[j2] = Xr[krow * kWavePanel + 4 + l3];
-                  b0i[j2] = CPLX ? Xi[krow * kWavePanel + l3] : 0.0;
-                  b1i[j2] = CPLX ? Xi[krow * kWavePanel + 4 + l3] : 0.0;
-                }
+                const int krow = kq[j2] * 4 + lq;
+                const long long a = (long long)krow * ld + tt * 16 + ln;
+                ar[j2] = Fr[a];
+                ai[j2] = CPLX ? Fi[a] : 0.0;
+                b0r[j2] = Xr[krow * kWavePanel + l3];
+                b1r[j2] = Xr[krow * kWavePanel + 4 + l3];
+                b0i[j2] = CPLX ? Xi[krow * kWavePanel + l3] : 0.0;
+                b1i[j2] = CPLX ? Xi[krow * kWavePanel + 4 + l3] : 0.0;
               }
 #pragma unroll
               for (int j2 = 0; j2 < kTileBatch; ++j2) {
