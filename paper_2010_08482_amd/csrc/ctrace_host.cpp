@@ -36,6 +36,7 @@ struct ctr_ctx {
   int grid_split7 = 0;  // FP32-split, 7 slices
   int slices = 6;       // slices of the current FP32-split call
   int grid_wave = 0;  // wavefront-per-panel kernel (panels of 8 columns), 0 = not applicable
+  int grid_wave_lazy = 0;  // its lazy form
   int grid_big = 0;   // streaming kernel
   int grid_group = 0;  // block-grouped rounds, 0 = not applicable
   int cw_group = 0;    // columns per grouped work item
@@ -317,7 +318,10 @@ ctr_status enqueue(ctr_ctx* ctx, BatchArgs& a, bool plan_only, bool split, Kerne
   ctx->last_kernel = kind == Kernel::Wave ? CTR_KERNEL_WAVE : kind == Kernel::Block ? CTR_KERNEL_BLOCK : CTR_KERNEL_STREAM;
   ctx->last_slices = split ? ctx->slices : 0;
   switch (kind) {
-    case Kernel::Wave: e = ctr::launch_chain_wave(ctx->imp, a, shared_grid(ctx, ctx->grid_wave, 1), ctx->stream); break;
+    case Kernel::Wave:
+      e = ctr::launch_chain_wave(ctx->imp, a, shared_grid(ctx, a.log_thr ? ctx->grid_wave_lazy : ctx->grid_wave, 1),
+                                 ctx->stream);
+      break;
     case Kernel::Block:
       e = ctr::launch_chain(ctx->imp, a, split ? ctx->slices : 0,
                             shared_grid(ctx, split ? (ctx->slices == 7 ? ctx->grid_split7 : ctx->grid_split) : ctx->grid, 1),
@@ -870,6 +874,7 @@ ctr_status ctr_set_impurity(ctr_ctx* ctx, const ctr_impurity* imp) {
   ctx->grid_split = ctr::chain_grid(ctx->imp, ctx->device, 6, nullptr);
   ctx->grid_split7 = ctr::chain_grid(ctx->imp, ctx->device, 7, nullptr);
   ctx->grid_wave = ctr::wave_grid(ctx->imp, ctx->device, nullptr);
+  ctx->grid_wave_lazy = ctr::wave_grid(ctx->imp, ctx->device, nullptr, true);
   ctx->grid_big = ctr::big_grid(ctx->imp, ctx->device, nullptr);
   ctx->cw_group = 0;
   ctx->rc_group = 0;

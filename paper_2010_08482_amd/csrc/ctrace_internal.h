@@ -179,7 +179,7 @@ int chain_grid(const DevImp& imp, int device, int split, size_t* lds_bytes);
 size_t chain_lds_bytes(const DevImp& imp);
 int chain_max_rows(int is_complex);
 // Wavefront-per-panel chain kernel (sectors of at most 128 states); grid 0 = not applicable.
-int wave_grid(const DevImp& imp, int device, size_t* lds_bytes);
+int wave_grid(const DevImp& imp, int device, size_t* lds_bytes, bool lazy = false);
 hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream);
 constexpr int kWavePanelHost = 8;
 // Streaming chain kernel (any sector size; X in per-workgroup global buffers).

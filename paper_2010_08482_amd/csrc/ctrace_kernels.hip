@@ -926,7 +926,7 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int xr, int n_sec, int next_
 }
 
 template <bool CPLX, bool LAZY>
-__global__ __launch_bounds__(256, CPLX ? 2 : 3) void k_chain_wave(DevImp I, BatchArgs B) {
+__global__ __launch_bounds__(256, CPLX ? 2 : (LAZY ? 3 : 4)) void k_chain_wave(DevImp I, BatchArgs B) {
   extern __shared__ double lds[];
   const int XR = I.xrows;
   const int NS = I.n_sec;
@@ -1717,7 +1717,7 @@ int chain_grid(const DevImp& imp, int device, int split, size_t* lds_bytes) {
   return per_cu * cus;
 }
 
-int wave_grid(const DevImp& imp, int device, size_t* lds_bytes) {
+int wave_grid(const DevImp& imp, int device, size_t* lds_bytes, bool lazy) {
   if (imp.xrows > kWaveTiles * 16) return 0;
   const int ne = imp.next_lds ? imp.n_sec * imp.nops : 0;
   const size_t bytes = imp.is_complex ? wave_lds_bytes<true>(imp.xrows, imp.n_sec, ne)
@@ -1728,16 +1728,18 @@ int wave_grid(const DevImp& imp, int device, size_t* lds_bytes) {
                                         : reinterpret_cast<const void*>(&k_chain_wave<false, false>),
                         imp.is_complex ? reinterpret_cast<const void*>(&k_chain_wave<true, true>)
                                         : reinterpret_cast<const void*>(&k_chain_wave<false, true>)};
-  int per_cu = 1 << 30;
-  for (const void* fn : fns) {
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
-    int k = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, fn, 256, bytes) != hipSuccess) return 0;
-    per_cu = std::min(per_cu, k);
+  // the plain and the lazy form are sized apart (the plain one runs four
+  // workgroups per CU, the lazy one, with its bound bookkeeping, three);
+  // neither is offered unless both can run
+  int per_cu[2] = {0, 0};
+  for (int v = 0; v < 2; ++v) {
+    if (hipFuncSetAttribute(fns[v], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[v], fns[v], 256, bytes) != hipSuccess) return 0;
   }
+  if (per_cu[0] <= 0 || per_cu[1] <= 0) return 0;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  return per_cu > 0 ? per_cu * cus : 0;
+  return per_cu[lazy ? 1 : 0] * cus;
 }
 
 hipError_t launch_chain_wave(const DevImp& imp, const BatchArgs& b, int grid, hipStream_t stream) {
