@@ -1017,13 +1017,17 @@ __global__ __launch_bounds__(256, CPLX ? 2 : (LAZY ? 3 : 4)) void k_chain_wave(D
 
       int ce[2] = {0, 0};  // power of two of columns g*4 + l3
       long long boff_next = I.boff[s0 * I.nops + s_op[0]];
+      int rj_prev = 0;  // lazy: the configuration's rejection flag, read one step earlier
       for (int t = 0; t < n - 1; ++t) {
         if (lazy) {
-          int rj = (lane == 0) ? (int)lazy_rejected(B, c) : 0;
-          if (__shfl(rj, 0)) {
+          // the flag read at the previous step decides; this step's read is
+          // issued now and waited for only at the next step, behind this
+          // step's products
+          if (__shfl(rj_prev, 0)) {
             dead = true;
             break;
           }
+          rj_prev = (lane == 0) ? (int)lazy_rejected(B, c) : 0;
         }
         const int s = s_path[t], s2 = s_path[t + 1];
         const int d_in = s_dim[s], d_out = s_dim[s2];
