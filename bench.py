@@ -105,8 +105,8 @@ def kernel_name(tab, kernel, slices):
 TRAFFIC_MEASURED = {
     ("k_chain_wave", "dshell-kanamori-10^4-orders20-80, 10000 per step"): {
         "source": "ctrace_kernels.hip",
-        "sha256": "24c6ab3e5bf7cd48dfd8f4f28980f65f145d8c4a66e3e95177d856a8627954af",
-        "bytes": 1.4627e9},
+        "sha256": "3dc1033163cc10ec655db74d0593e1d526dcdbbb8b63403c0bc60f246ecfe420",
+        "bytes": 1.4633e9},
     ("k_gbig", "fshell-slater-soc-cf-2000-orders60-200, 200 per step"): {
         "source": "ctrace_group.hip",
         "sha256": "f458b6d1e0ebe63f942ac8f8f82525dfb984b8f09892ec165c47a78127a1898c",
