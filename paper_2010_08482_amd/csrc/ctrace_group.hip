@@ -698,7 +698,7 @@ __global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, Gr
   // KC: rows of X staged in LDS per chunk
   constexpr int LDB = KC + 1;            // odd stride: the 16 columns of a B fragment hit distinct banks
   constexpr int PL = CPLX ? 2 : 1;
-  __shared__ double sB[PL * CW * LDB];
+  __shared__ double sB[2 * PL * CW * LDB];  // two staging buffers: chunk c in buffer c % 2
   __shared__ double s_cmax[WR * CW];
   __shared__ double s_dt[CW];
   __shared__ double s_sc[CW];
@@ -847,14 +847,17 @@ __global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, Gr
     fetch(0, min(KC, kp));
     for (int k0 = 0; k0 < kp; k0 += KC) {
       const int kc = min(KC, kp - k0);
-      if (k0 > 0) __syncthreads();  // previous chunk consumed
+      // one barrier per chunk: the buffer written here was last read two chunks
+      // ago, and every wavefront finished that chunk before the barrier of the
+      // chunk in between
+      double* sBc = sB + ((k0 / KC) & 1) * PL * CW * LDB;
 #pragma unroll
       for (int u = 0; u < NPF; ++u) {
         const int idx = tid + u * NT;
         if (idx < CW * kc) {
           const int j = idx / kc, kk = idx - j * kc;
-          sB[j * LDB + kk] = pf_r[u];
-          if (CPLX) sB[CW * LDB + j * LDB + kk] = pf_i[u];
+          sBc[j * LDB + kk] = pf_r[u];
+          if (CPLX) sBc[CW * LDB + j * LDB + kk] = pf_i[u];
         }
       }
       __syncthreads();
@@ -885,8 +888,8 @@ __global__ __launch_bounds__(WR * WC * 64) void k_gbig(DevImp I, BatchArgs B, Gr
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
               const int jb = (wc * CT + t) * 16 + ln;
-              const double br = sB[jb * LDB + kk + lq];
-              const double bi = CPLX ? sB[CW * LDB + jb * LDB + kk + lq] : 0.0;
+              const double br = sBc[jb * LDB + kk + lq];
+              const double bi = CPLX ? sBc[CW * LDB + jb * LDB + kk + lq] : 0.0;
 #pragma unroll
               for (int i = 0; i < RT; ++i) {
                 if (tile0 + i < ntiles) {
@@ -1613,8 +1616,9 @@ bool pick_gvariant(const DevImp& imp, int alt, GVariant* v, int split = 0) {
     // row-chunked items at any size (alt 2 and 3: the two tile shapes).  A sweep of 14 shapes on the
     // crystal-field f-shell (200 configurations) put 16 wavefronts x one row tile x two column tiles
     // (256 rows x 32 columns, 4 wavefronts per SIMD) first at 16.0 traces/s, 8 x 2 x 2 at 14.4,
-    // 4 x 2 column groups of 2 x 2 at 12.3; chunks of 16, 32 or 64 staged rows of X were alike
-    if (imp.is_complex) *v = alt == 3 ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2>();
+    // 4 x 2 column groups of 2 x 2 at 12.3; with the staging double-buffered, chunks of 16 rows of X
+    // reach 16.4 (32 rows: 16.0, 8 rows spill)
+    if (imp.is_complex) *v = alt == 3 ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2, 16>();
     else *v = alt == 3 ? make_bvariant<false, 8, 1, 2, 2>() : make_bvariant<false, 16, 1, 1, 2>();
     return alt <= 3;
   }
@@ -1622,7 +1626,7 @@ bool pick_gvariant(const DevImp& imp, int alt, GVariant* v, int split = 0) {
     if (tiles <= 2) *v = make_wvariant<true, 2>();
     else if (tiles <= 8) *v = make_gvariant<true, 4, 2, 2>();
     else if (tiles <= 24) *v = alt ? make_gvariant<true, 8, 3, 2>() : make_gvariant<true, 12, 2, 2>();
-    else *v = alt ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2>();
+    else *v = alt ? make_bvariant<true, 8, 1, 2, 2>() : make_bvariant<true, 16, 1, 1, 2, 16>();
     return !alt || tiles > 8;
   }
   if (tiles <= 2) *v = make_wvariant<false, 2>();
