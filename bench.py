@@ -109,12 +109,12 @@ TRAFFIC_MEASURED = {
         "bytes": 1.4633e9},
     ("k_gbig", "fshell-slater-soc-cf-2000-orders60-200, 200 per step"): {
         "source": "ctrace_group.hip",
-        "sha256": "d2246808112b4c9693d8e5012f262fbeb12cd1731051cb2cdc2fdfbe3d3a28cc",
-        "bytes": 200.420e9},
+        "sha256": "d710a66bffc9cc6f77b33b6e8bee79d06a15acdf92fce1b463f65a884267d5ff",
+        "bytes": 199.341e9},
     ("k_gstep", "fshell-slater-soc-10^4-orders40-160, 10000 per step"): {
         "source": "ctrace_group.hip",
-        "sha256": "d2246808112b4c9693d8e5012f262fbeb12cd1731051cb2cdc2fdfbe3d3a28cc",
-        "bytes": 26.302e9},
+        "sha256": "d710a66bffc9cc6f77b33b6e8bee79d06a15acdf92fce1b463f65a884267d5ff",
+        "bytes": 26.513e9},
 }
 
 

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
   constexpr int KC = 64;                 // rows of X staged in LDS per chunk
   constexpr int LDB = KC + 1;            // odd stride: the 16 columns of a B fragment hit distinct banks
   constexpr int PL = CPLX ? 2 : 1;
-  __shared__ double sB[PL * CW * LDB];
+  __shared__ double sB[2 * PL * CW * LDB];  // two staging buffers: chunk c in buffer c % 2
   __shared__ double s_cmax[NW * CW];
   __shared__ double s_dt[CW];
   __shared__ long long s_gcol[CW];
@@ -561,13 +561,17 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
       }
     for (int k0 = 0; k0 < kp; k0 += KC) {
       const int kc = min(KC, kp - k0);
-      __syncthreads();  // previous chunk consumed; s_gcol visible
+      // one barrier per chunk after the first: the buffer written here was last
+      // read two chunks ago, which every wavefront finished before the barrier
+      // of the chunk in between
+      double* sBc = sB + ((k0 / KC) & 1) * PL * CW * LDB;
+      if (k0 == 0) __syncthreads();  // s_gcol visible; the previous item's reads done
       for (int idx = tid; idx < CW * kc; idx += NT) {
         const int j = idx / kc, kk = idx - j * kc;
         const long long g = s_gcol[j];
         const long long a = g * XR + k0 + kk;
-        sB[j * LDB + kk] = g >= 0 ? Xin[a] : 0.0;
-        if (CPLX) sB[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] : 0.0;
+        sBc[j * LDB + kk] = g >= 0 ? Xin[a] : 0.0;
+        if (CPLX) sBc[CW * LDB + j * LDB + kk] = g >= 0 ? Xin[plane + a] : 0.0;
       }
       __syncthreads();
       for (int kb = 0; kb < kc; kb += 4 * kPD) {
@@ -595,8 +599,8 @@ __global__ __launch_bounds__(NW * 64) void k_gstep(DevImp I, BatchArgs B, GroupA
             }
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-              const double br = sB[(t * 16 + ln) * LDB + kk + lq];
-              const double bi = CPLX ? sB[CW * LDB + (t * 16 + ln) * LDB + kk + lq] : 0.0;
+              const double br = sBc[(t * 16 + ln) * LDB + kk + lq];
+              const double bi = CPLX ? sBc[CW * LDB + (t * 16 + ln) * LDB + kk + lq] : 0.0;
 #pragma unroll
               for (int i = 0; i < RT; ++i) {
                 if (wave + i * NW < ntiles) {
