@@ -87,12 +87,23 @@ def workload_set(name, impurity, config_id, indices, store):
     `store`, zero columns dropped).  The file is rewritten after every string."""
     imp = make_impurity(impurity)
     t0 = time.time()
+    # strings already in the file (from an earlier run of this set) are kept, not recomputed
+    path = os.path.join(HERE, name + ".json")
+    done = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+        if old.get("impurity") == impurity and old.get("config_id") == config_id:
+            done = {int(r["i"]): r for r in old["records"]}
     os.makedirs(store, exist_ok=True)
     dt = DenseTrace(imp, op_store=store)
     print(f"{name}: eigenbasis in {time.time() - t0:.0f}s", flush=True)
     cfgs = make_configs(config_id, max(indices) + 1)
     out = []
     for i in indices:
+        if i in done:
+            out.append(done[i])
+            continue
         s = cfgs[i]
         (m, l), (a, la) = dt.trace_and_scale(s.tau, s.op)
         m = complex(m)
@@ -118,9 +129,9 @@ SETS = {
     # cheapest for the dense oracle among its first 400 configurations of order <= 44)
     "fshell_workload": lambda: workload_set("fshell_workload", "fshell", 2, [93, 391],
                                             os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell")),
-    # a production-order string of the crystal-field f-shell benchmark (order 60, its lowest; the
+    # production-order strings of the crystal-field f-shell benchmark (order 60, its lowest; the two
     # cheapest for the dense oracle among the 26 of order 60 in its 2000 configurations)
-    "fshell_cf_workload": lambda: workload_set("fshell_cf_workload", "fshell_cf", 3, [480],
+    "fshell_cf_workload": lambda: workload_set("fshell_cf_workload", "fshell_cf", 3, [480, 1667],
                                                os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell_cf")),
 }
 
