@@ -118,9 +118,17 @@ def test_D4_quadrature_in_the_occupation_basis(name):
     quadrature of the cut products in the occupation basis (expm propagators):
     a swapped pair (u, v) in the interval integral, a wrong interval or a
     misplaced cut moves the result far beyond the bar."""
+    from threadpoolctl import threadpool_limits
+
     imp = make_impurity(name)
     dt = DenseTrace(imp)
     rng = np.random.Generator(np.random.PCG64(403))
+    # many small (64 x 64) matrix exponentials: BLAS threads only add synchronisation
+    with threadpool_limits(limits=1):
+        _check_quadrature(imp, dt, rng)
+
+
+def _check_quadrature(imp, dt, rng):
     seen = 0
     for _ in range(4):
         s = random_string(rng, imp.n_flavors, imp.beta, 2 * int(rng.integers(1, 3)), "alternating")
