@@ -1074,7 +1074,8 @@ def test_histogram_over_sector_index_labels(lib, ctx):
 
 
 @pytest.mark.parametrize("name,cid,count,kernels", [("dshell", 1, 256, ("wave", "grouped")),
-                                                    ("fshell", 2, 48, ("block", "grouped"))])
+                                                    ("fshell", 2, 48, ("block", "grouped")),
+                                                    ("fshell_cf", 3, 8, ("stream", "grouped_rows"))])
 def test_histogram_full_size_sum_rule_and_kernels_agree(lib, ctx, name, cid, count, kernels):
     """Full-size impurities: the labels of every nonzero configuration sum to
     one, and two chain kernels agree, both within 1e-10 times the
