@@ -125,9 +125,9 @@ SETS = {
     # the generic f-shell impurities of the (N, Jz) and crystal-field workloads at full size
     "fshell_low": lambda: low_order_set("fshell_low", "fshell", 81, [2, 2, 2, 4]),
     "fshell_cf_low": lambda: low_order_set("fshell_cf_low", "fshell_cf", 82, [2, 2, 4]),
-    # production-order workload strings of the f-shell (N, Jz) benchmark (orders 44 and 40; the two
+    # production-order workload strings of the f-shell (N, Jz) benchmark (orders 44, 40 and 42; the three
     # cheapest for the dense oracle among its first 400 configurations of order <= 44)
-    "fshell_workload": lambda: workload_set("fshell_workload", "fshell", 2, [93, 391],
+    "fshell_workload": lambda: workload_set("fshell_workload", "fshell", 2, [93, 391, 16],
                                             os.environ.get("ORACLE_OP_STORE", "/tmp/oracle_ops_fshell")),
     # production-order strings of the crystal-field f-shell benchmark (order 60, its lowest; the two
     # cheapest for the dense oracle among the 26 of order 60 in its 2000 configurations)
